@@ -1,0 +1,518 @@
+// Oracle for the GPUexplore-style exploration path (arXiv 1801.05857).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct CPU
+// model of what the GPU library computes.  Only the test suite, the smoke check
+// and the CPU-baseline leg of the benchmark may load it.  It shares no code,
+// header, constant or helper with the GPU library, and it includes nothing from
+// the package.
+//
+// What it computes, and where the paper defines it:
+//   * find-or-put (Sec. 4.1): inserting a vector either finds it already stored
+//     or stores it.  Sequentially that is set insertion; the oracle is
+//     std::unordered_set::insert, and a key is NEW exactly at its first
+//     occurrence in the stream.
+//   * exploration (Sec. 3, Fig. 1): breadth-first construction of the reachable
+//     part of the synchronous product of a network of LTSs, layer by layer,
+//     with deadlock detection (states without an outgoing product transition).
+//   * packing (Sec. 3 and Sec. 5.2): process states are packed into 32-bit
+//     integers; a vector that needs more than one integer spans several words.
+//
+// Readings of points the paper leaves open (each is listed with its reason in
+// the design notes of the repository):
+//   * A transition of process p whose label is named at position p of some
+//     synchronisation rule fires only through such rules, all participants of
+//     the rule stepping together; every other transition fires alone.  (Fig. 1
+//     and its count of 8 states and 24 transitions, Sec. 3.)
+//   * One product transition per local transition fired alone, and one per
+//     choice of one matching transition for every participant of a rule.  No
+//     merging of parallel product transitions.
+//   * Field width of process p: max(1, ceil(log2 n_p)) bits; fields are laid
+//     out in process order from the least significant bit, never straddle a
+//     word, and only bits 0..30 of a word are used, so bit 31 is always 0.
+//   * Level k holds the states at BFS distance k; level 0 is the initial state.
+//   * Deadlocks and set dumps are sorted lexicographically by (word0, word1,
+//     ...) as unsigned integers.
+//
+// Parity pins (tests/test_oracle_pins.py): Fig. 1 counts, the Token Ring state
+// counts of Table 1, closed forms for products of independent cycles and for
+// the tiny four-process network, hand-packed vectors, and the brute-force
+// fixpoint enumerator below (a different algorithm and data structure).
+
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <unordered_set>
+#include <vector>
+
+namespace {
+
+constexpr uint32_t kMaxWords = 4;
+using Vec = std::array<uint32_t, kMaxWords>;  // unused words stay 0
+
+struct VecHash {
+  // FNV-1a over the four words: a plain hash for std::unordered_set.
+  size_t operator()(const Vec& v) const noexcept {
+    uint64_t h = 1469598103934665603ULL;
+    for (uint32_t x : v) {
+      for (int b = 0; b < 4; ++b) {
+        h ^= (x >> (8 * b)) & 0xFFu;
+        h *= 1099511628211ULL;
+      }
+    }
+    return static_cast<size_t>(h);
+  }
+};
+
+using VecSet = std::unordered_set<Vec, VecHash>;
+
+bool vec_less(const Vec& a, const Vec& b) {
+  for (uint32_t i = 0; i < kMaxWords; ++i) {
+    if (a[i] != b[i]) return a[i] < b[i];
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------- packing
+struct Plan {
+  uint32_t words = 0;
+  std::vector<uint32_t> word_of, shift_of, width_of;
+};
+
+uint32_t field_width(uint32_t n_states) {
+  // smallest b >= 1 with 2^b >= n_states
+  uint32_t b = 1;
+  while (b < 32 && (uint64_t(1) << b) < n_states) ++b;
+  return b;
+}
+
+bool make_plan(uint32_t P, const uint32_t* n_states, Plan* plan) {
+  plan->word_of.assign(P, 0);
+  plan->shift_of.assign(P, 0);
+  plan->width_of.assign(P, 0);
+  uint32_t word = 0, used = 0;
+  for (uint32_t p = 0; p < P; ++p) {
+    if (n_states[p] == 0) return false;
+    uint32_t b = field_width(n_states[p]);
+    if (b > 31) return false;
+    if (used + b > 31) {  // would straddle: start a fresh word
+      ++word;
+      used = 0;
+    }
+    plan->word_of[p] = word;
+    plan->shift_of[p] = used;
+    plan->width_of[p] = b;
+    used += b;
+  }
+  plan->words = (P == 0) ? 0 : word + 1;
+  return true;
+}
+
+Vec pack(const Plan& plan, const std::vector<uint32_t>& local) {
+  Vec v{};
+  for (size_t p = 0; p < local.size(); ++p) {
+    v[plan.word_of[p]] |= local[p] << plan.shift_of[p];
+  }
+  return v;
+}
+
+std::vector<uint32_t> unpack(const Plan& plan, const Vec& v) {
+  std::vector<uint32_t> local(plan.word_of.size());
+  for (size_t p = 0; p < local.size(); ++p) {
+    uint32_t mask = (plan.width_of[p] == 32) ? 0xFFFFFFFFu : ((1u << plan.width_of[p]) - 1u);
+    local[p] = (v[plan.word_of[p]] >> plan.shift_of[p]) & mask;
+  }
+  return local;
+}
+
+// ---------------------------------------------------------------- network
+struct Trans {
+  uint32_t label, dst;
+};
+
+struct Net {
+  uint32_t P = 0, n_labels = 0, R = 0;
+  std::vector<uint32_t> n_states, initial;
+  // out[p][s] = transitions leaving local state s of process p
+  std::vector<std::vector<std::vector<Trans>>> out;
+  std::vector<int32_t> rules;  // R x P, label or -1
+  // governed[p][a]: label a is named at position p by some rule
+  std::vector<std::vector<bool>> governed;
+};
+
+bool load_net(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+              const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+              const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
+              Net* net) {
+  net->P = P;
+  net->n_labels = n_labels;
+  net->R = R;
+  net->n_states.assign(n_states, n_states + P);
+  net->initial.assign(initial, initial + P);
+  net->out.assign(P, {});
+  net->governed.assign(P, std::vector<bool>(n_labels, false));
+  uint64_t base = 0;
+  for (uint32_t p = 0; p < P; ++p) {
+    if (n_states[p] == 0 || initial[p] >= n_states[p]) return false;
+    net->out[p].assign(n_states[p], {});
+    for (uint32_t t = 0; t < n_trans[p]; ++t) {
+      uint32_t s = src[base + t], a = label[base + t], d = dst[base + t];
+      if (s >= n_states[p] || d >= n_states[p] || a >= n_labels) return false;
+      net->out[p][s].push_back({a, d});
+    }
+    base += n_trans[p];
+  }
+  net->rules.assign(rules, rules + size_t(R) * P);
+  for (uint32_t r = 0; r < R; ++r) {
+    uint32_t parts = 0;
+    for (uint32_t p = 0; p < P; ++p) {
+      int32_t a = net->rules[size_t(r) * P + p];
+      if (a < -1 || a >= int32_t(n_labels)) return false;
+      if (a >= 0) {
+        net->governed[p][a] = true;
+        ++parts;
+      }
+    }
+    if (parts == 0) return false;
+  }
+  return true;
+}
+
+// All product successors of the unpacked state `local`, with multiplicity.
+void successors(const Net& net, const std::vector<uint32_t>& local,
+                std::vector<std::vector<uint32_t>>* succ) {
+  succ->clear();
+  // transitions that fire alone
+  for (uint32_t p = 0; p < net.P; ++p) {
+    for (const Trans& t : net.out[p][local[p]]) {
+      if (net.governed[p][t.label]) continue;
+      std::vector<uint32_t> s = local;
+      s[p] = t.dst;
+      succ->push_back(std::move(s));
+    }
+  }
+  // synchronisation rules: every participant takes one matching transition
+  for (uint32_t r = 0; r < net.R; ++r) {
+    std::vector<uint32_t> parts;
+    for (uint32_t p = 0; p < net.P; ++p) {
+      if (net.rules[size_t(r) * net.P + p] >= 0) parts.push_back(p);
+    }
+    std::vector<uint32_t> cur = local;
+    std::function<void(size_t)> choose = [&](size_t i) {
+      if (i == parts.size()) {
+        succ->push_back(cur);
+        return;
+      }
+      uint32_t q = parts[i];
+      uint32_t want = uint32_t(net.rules[size_t(r) * net.P + q]);
+      for (const Trans& t : net.out[q][local[q]]) {
+        if (t.label != want) continue;
+        cur[q] = t.dst;
+        choose(i + 1);
+      }
+      cur[q] = local[q];
+    };
+    choose(0);
+  }
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+// ======================================================================
+extern "C" {
+
+// ---- set (find-or-put oracle) ----------------------------------------
+struct oracle_set {
+  uint32_t w;
+  VecSet set;
+};
+
+oracle_set* oracle_set_new(uint32_t w) {
+  if (w == 0 || w > kMaxWords) return nullptr;
+  oracle_set* s = new oracle_set;
+  s->w = w;
+  return s;
+}
+
+void oracle_set_free(oracle_set* s) { delete s; }
+
+uint64_t oracle_set_size(const oracle_set* s) { return s->set.size(); }
+
+// Insert keys[0..n) (row-major, w words each) in order.  status[i] = 1 when
+// key i was not in the set before its insertion, else 0.  Returns the number
+// of keys that were new.
+uint64_t oracle_set_insert(oracle_set* s, const uint32_t* keys, uint64_t n, uint8_t* status) {
+  uint64_t fresh = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    Vec v{};
+    for (uint32_t k = 0; k < s->w; ++k) v[k] = keys[i * s->w + k];
+    bool inserted = s->set.insert(v).second;
+    if (status) status[i] = inserted ? 1 : 0;
+    fresh += inserted ? 1 : 0;
+  }
+  return fresh;
+}
+
+int oracle_set_contains(const oracle_set* s, const uint32_t* key) {
+  Vec v{};
+  for (uint32_t k = 0; k < s->w; ++k) v[k] = key[k];
+  return s->set.count(v) ? 1 : 0;
+}
+
+// Write the set, sorted lexicographically, as size*w words.
+void oracle_set_dump(const oracle_set* s, uint32_t* out) {
+  std::vector<Vec> all(s->set.begin(), s->set.end());
+  std::sort(all.begin(), all.end(), vec_less);
+  for (size_t i = 0; i < all.size(); ++i) {
+    for (uint32_t k = 0; k < s->w; ++k) out[i * s->w + k] = all[i][k];
+  }
+}
+
+// ---- packing plan -----------------------------------------------------
+// Returns 0 and the number of words on success, -1 when a process has no
+// states or a field would need more than 31 bits.
+int oracle_pack_plan(uint32_t P, const uint32_t* n_states, uint32_t* word_of,
+                     uint32_t* shift_of, uint32_t* width_of, uint32_t* words) {
+  Plan plan;
+  if (!make_plan(P, n_states, &plan)) return -1;
+  for (uint32_t p = 0; p < P; ++p) {
+    if (word_of) word_of[p] = plan.word_of[p];
+    if (shift_of) shift_of[p] = plan.shift_of[p];
+    if (width_of) width_of[p] = plan.width_of[p];
+  }
+  *words = plan.words;
+  return 0;
+}
+
+// Pack n unpacked states (n x P local states) into n x words words.
+int oracle_pack(uint32_t P, const uint32_t* n_states, const uint32_t* local, uint64_t n,
+                uint32_t* out) {
+  Plan plan;
+  if (!make_plan(P, n_states, &plan)) return -1;
+  for (uint64_t i = 0; i < n; ++i) {
+    std::vector<uint32_t> l(local + i * P, local + (i + 1) * P);
+    Vec v = pack(plan, l);
+    for (uint32_t k = 0; k < plan.words; ++k) out[i * plan.words + k] = v[k];
+  }
+  return 0;
+}
+
+// ---- exploration --------------------------------------------------------
+struct oracle_result {
+  uint32_t words;
+  uint32_t n_levels;
+  uint64_t n_states;
+  uint64_t n_transitions;
+  uint64_t* levels;       // n_levels
+  uint64_t n_deadlocks;
+  uint32_t* deadlocks;    // n_deadlocks x words, sorted
+  uint32_t* visited;      // n_states x words, sorted (only when requested)
+};
+
+void oracle_result_free(oracle_result* r) {
+  if (!r) return;
+  std::free(r->levels);
+  std::free(r->deadlocks);
+  std::free(r->visited);
+  r->levels = nullptr;
+  r->deadlocks = nullptr;
+  r->visited = nullptr;
+}
+
+static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
+                        uint64_t n_states, uint64_t n_transitions, std::vector<Vec>& dead,
+                        std::vector<Vec>* visited, oracle_result* out) {
+  std::sort(dead.begin(), dead.end(), vec_less);
+  out->words = plan.words;
+  out->n_levels = uint32_t(levels.size());
+  out->n_states = n_states;
+  out->n_transitions = n_transitions;
+  out->levels = static_cast<uint64_t*>(std::malloc(sizeof(uint64_t) * (levels.size() + 1)));
+  for (size_t i = 0; i < levels.size(); ++i) out->levels[i] = levels[i];
+  out->n_deadlocks = dead.size();
+  out->deadlocks =
+      static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (dead.size() * plan.words + 1)));
+  for (size_t i = 0; i < dead.size(); ++i)
+    for (uint32_t k = 0; k < plan.words; ++k) out->deadlocks[i * plan.words + k] = dead[i][k];
+  out->visited = nullptr;
+  if (visited) {
+    std::sort(visited->begin(), visited->end(), vec_less);
+    out->visited = static_cast<uint32_t*>(
+        std::malloc(sizeof(uint32_t) * (visited->size() * plan.words + 1)));
+    for (size_t i = 0; i < visited->size(); ++i)
+      for (uint32_t k = 0; k < plan.words; ++k)
+        out->visited[i * plan.words + k] = (*visited)[i][k];
+  }
+}
+
+// Plain breadth-first search over std::unordered_set.
+// Returns 0 on success, -1 on an invalid network, -2 when more than
+// max_states states are reachable (max_states == 0: no limit).
+int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                   const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                   const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
+                   uint64_t max_states, int want_visited, oracle_result* out) {
+  Net net;
+  Plan plan;
+  if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
+                          &net))
+    return -1;
+  if (!make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
+
+  VecSet visited;
+  std::vector<Vec> frontier, next, dead;
+  std::vector<uint64_t> levels;
+  uint64_t transitions = 0;
+  std::vector<std::vector<uint32_t>> succ;
+
+  Vec init = pack(plan, net.initial);
+  visited.insert(init);
+  frontier.push_back(init);
+  levels.push_back(1);
+  while (!frontier.empty()) {
+    next.clear();
+    for (const Vec& s : frontier) {
+      successors(net, unpack(plan, s), &succ);
+      transitions += succ.size();
+      if (succ.empty()) dead.push_back(s);
+      for (const auto& t : succ) {
+        Vec v = pack(plan, t);
+        if (visited.insert(v).second) next.push_back(v);
+      }
+      if (max_states && visited.size() > max_states) return -2;
+    }
+    if (!next.empty()) levels.push_back(next.size());
+    frontier.swap(next);
+  }
+  std::vector<Vec> vis;
+  if (want_visited) vis.assign(visited.begin(), visited.end());
+  fill_result(plan, levels, visited.size(), transitions, dead, want_visited ? &vis : nullptr,
+              out);
+  return 0;
+}
+
+// Brute-force fixpoint over a dense bitmap of every vector of local states
+// (mixed-radix index over n_p), a different algorithm and data structure from
+// the BFS above: R_0 = {init}, R_{k+1} = R_k  union  post(R_k), recomputing post of
+// the whole set at every step.  Level k = |R_k \ R_{k-1}|.  Requires
+// prod n_p <= 2^24.  Same return codes as oracle_explore (-2: too large).
+int oracle_bruteforce(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                      const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                      const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
+                      int want_visited, oracle_result* out) {
+  Plan plan;
+  if (P == 0 || !make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
+  uint64_t total = 1;
+  for (uint32_t p = 0; p < P; ++p) {
+    if (n_states[p] == 0 || initial[p] >= n_states[p]) return -1;
+    total *= n_states[p];
+    if (total > (uint64_t(1) << 24)) return -2;
+  }
+  // flat transition list per process, scanned in full for every state
+  std::vector<uint64_t> first(P + 1, 0);
+  for (uint32_t p = 0; p < P; ++p) first[p + 1] = first[p] + n_trans[p];
+  for (uint32_t p = 0; p < P; ++p)
+    for (uint64_t t = first[p]; t < first[p + 1]; ++t)
+      if (src[t] >= n_states[p] || dst[t] >= n_states[p] || label[t] >= n_labels) return -1;
+  auto named_at = [&](uint32_t p, uint32_t a) {
+    for (uint32_t r = 0; r < R; ++r)
+      if (rules[size_t(r) * P + p] == int32_t(a)) return true;
+    return false;
+  };
+  for (uint32_t r = 0; r < R; ++r) {
+    bool any = false;
+    for (uint32_t p = 0; p < P; ++p) {
+      int32_t a = rules[size_t(r) * P + p];
+      if (a < -1 || a >= int32_t(n_labels)) return -1;
+      any |= a >= 0;
+    }
+    if (!any) return -1;
+  }
+  std::vector<uint64_t> radix(P, 1);
+  for (uint32_t p = 1; p < P; ++p) radix[p] = radix[p - 1] * n_states[p - 1];
+  auto digit = [&](uint64_t idx, uint32_t p) { return (idx / radix[p]) % n_states[p]; };
+
+  // post(idx): all successor indices with multiplicity
+  auto post = [&](uint64_t idx, std::vector<uint64_t>* res) {
+    res->clear();
+    for (uint32_t p = 0; p < P; ++p) {
+      uint64_t cur = digit(idx, p);
+      for (uint64_t t = first[p]; t < first[p + 1]; ++t) {
+        if (src[t] != cur || named_at(p, label[t])) continue;
+        res->push_back(idx - cur * radix[p] + uint64_t(dst[t]) * radix[p]);
+      }
+    }
+    for (uint32_t r = 0; r < R; ++r) {
+      // iterative odometer over the participants' matching transitions
+      std::vector<uint32_t> parts;
+      std::vector<std::vector<uint64_t>> choices;
+      bool blocked = false;
+      for (uint32_t p = 0; p < P && !blocked; ++p) {
+        int32_t a = rules[size_t(r) * P + p];
+        if (a < 0) continue;
+        std::vector<uint64_t> c;
+        uint64_t cur = digit(idx, p);
+        for (uint64_t t = first[p]; t < first[p + 1]; ++t)
+          if (src[t] == cur && label[t] == uint32_t(a)) c.push_back(t);
+        if (c.empty()) blocked = true;
+        parts.push_back(p);
+        choices.push_back(std::move(c));
+      }
+      if (blocked) continue;
+      std::vector<size_t> pick(parts.size(), 0);
+      while (true) {
+        uint64_t v = idx;
+        for (size_t i = 0; i < parts.size(); ++i) {
+          uint32_t p = parts[i];
+          v = v - digit(idx, p) * radix[p] + uint64_t(dst[choices[i][pick[i]]]) * radix[p];
+        }
+        res->push_back(v);
+        size_t i = 0;
+        while (i < parts.size() && ++pick[i] == choices[i].size()) pick[i++] = 0;
+        if (i == parts.size()) break;
+      }
+    }
+  };
+
+  uint64_t init = 0;
+  for (uint32_t p = 0; p < P; ++p) init += uint64_t(initial[p]) * radix[p];
+  std::vector<uint8_t> in(total, 0), nxt;
+  in[init] = 1;
+  std::vector<uint64_t> levels{1};
+  std::vector<uint64_t> res;
+  while (true) {
+    nxt = in;
+    for (uint64_t i = 0; i < total; ++i) {
+      if (!in[i]) continue;
+      post(i, &res);
+      for (uint64_t v : res) nxt[v] = 1;
+    }
+    uint64_t added = 0;
+    for (uint64_t i = 0; i < total; ++i) added += (nxt[i] && !in[i]) ? 1 : 0;
+    if (added == 0) break;
+    levels.push_back(added);
+    in.swap(nxt);
+  }
+  uint64_t n_reach = 0, transitions = 0;
+  std::vector<Vec> dead, vis;
+  std::vector<uint32_t> local(P);
+  for (uint64_t i = 0; i < total; ++i) {
+    if (!in[i]) continue;
+    ++n_reach;
+    post(i, &res);
+    transitions += res.size();
+    for (uint32_t p = 0; p < P; ++p) local[p] = uint32_t(digit(i, p));
+    Vec v = pack(plan, local);
+    if (res.empty()) dead.push_back(v);
+    if (want_visited) vis.push_back(v);
+  }
+  fill_result(plan, levels, n_reach, transitions, dead, want_visited ? &vis : nullptr, out);
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module only *produces inputs*: networks of LTSs and key streams.  It holds
+none of the method's arithmetic (no packing, hashing, successor generation or
+set logic), so both the GPU library and the CPU oracle can be fed from it
+without sharing code with each other.
+
+All randomness comes from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), written out here from its
+published definition.
+
+Networks follow the model of Sec. 3 of the paper: a network is a list of LTSs
+(states, labelled transitions, initial state) plus synchronisation rules, one
+row per rule with a label per process or -1 for "does not take part".
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+M64 = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+
+
+# --------------------------------------------------------------------- RNG
+class SplitMix64:
+    """Scalar SplitMix64 stream."""
+
+    def __init__(self, seed: int):
+        self.state = seed & M64
+
+    def next(self) -> int:
+        self.state = (self.state + GOLDEN) & M64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        return z ^ (z >> 31)
+
+    def below(self, k: int) -> int:
+        """Uniform integer in [0, k) by multiply-high range reduction."""
+        return (self.next() * k) >> 64
+
+    def chance(self, p: float) -> bool:
+        return self.next() < int(p * 2.0**64)
+
+
+# ---------------------------------------------------------------- networks
+@dataclass
+class Network:
+    """A network of LTSs with synchronisation rules (Sec. 3, Fig. 1).
+
+    ``trans[p]`` is a (k, 3) uint32 array of (src, label, dst) for process p;
+    ``rules`` is an (R, P) int32 array holding, per rule, the label each
+    participating process must take, or -1 for processes that do not take part.
+    """
+
+    n_states: np.ndarray
+    initial: np.ndarray
+    trans: list
+    n_labels: int
+    rules: np.ndarray
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_procs(self) -> int:
+        return int(len(self.n_states))
+
+    @property
+    def n_transitions_local(self) -> int:
+        return int(sum(t.shape[0] for t in self.trans))
+
+
+def _net(n_states, initial, trans, n_labels, rules, name, **meta) -> Network:
+    P = len(n_states)
+    return Network(
+        n_states=np.asarray(n_states, dtype=np.uint32),
+        initial=np.asarray(initial, dtype=np.uint32),
+        trans=[np.asarray(t, dtype=np.uint32).reshape(-1, 3) for t in trans],
+        n_labels=int(n_labels),
+        rules=np.asarray(rules, dtype=np.int32).reshape(-1, P),
+        name=name,
+        meta=dict(meta),
+    )
+
+
+def fig1_producer_consumers() -> Network:
+    """The producer / two-consumer network of Fig. 1.
+
+    Labels: 0 tau, 1 gen_work, 2 send, 3 rec, 4 work.  Producer: p0 -gen_work->
+    p1 -send-> p0.  Consumer: c0 -rec-> c1, c1 -work-> c1, c1 -tau-> c0.  Rules
+    (send, rec, _) and (send, _, rec).
+    """
+    producer = [(0, 1, 1), (1, 2, 0)]
+    consumer = [(0, 3, 1), (1, 4, 1), (1, 0, 0)]
+    rules = [[2, 3, -1], [2, -1, 3]]
+    return _net([2, 2, 2], [0, 0, 0], [producer, consumer, consumer], 5, rules, "fig1")
+
+
+def tiny_cycles() -> Network:
+    """Four cyclic processes of 8 local states with free tau steps s -> s+1 mod 8,
+    plus one rendezvous label r (an edge 0 -> 4 in every process) synchronising
+    processes 0-1 and processes 2-3.  Labels: 0 tau, 1 r.  Fits one word
+    (4 x 3 bits)."""
+    proc = [(s, 0, (s + 1) % 8) for s in range(8)] + [(0, 1, 4)]
+    rules = [[1, 1, -1, -1], [-1, -1, 1, 1]]
+    return _net([8] * 4, [0] * 4, [proc] * 4, 2, rules, "tiny_cycles")
+
+
+def independent_cycles(sizes) -> Network:
+    """Processes that are plain tau cycles of the given sizes, no rules."""
+    trans = [[(s, 0, (s + 1) % n) for s in range(n)] for n in sizes]
+    return _net(list(sizes), [0] * len(sizes), trans, 1, np.zeros((0, len(sizes))),
+                "cycles_" + "x".join(str(n) for n in sizes))
+
+
+def token_ring(n: int) -> Network:
+    """One token passed around a ring of n nodes (the Token Ring of Sec. 5.2).
+
+    Node LTS, 5 states: A -tau-> B -tau-> C -rec-> T1 -tau-> T2 -send-> A, i.e.
+    three internal transitions and two communication transitions per node.
+    Rule i pairs send of node i with rec of node (i+1) mod n.  Node 0 starts
+    holding the token (T1), the others in A.  Labels: 0 tau, 1 send, 2 rec.
+    """
+    A, B, C, T1, T2 = range(5)
+    node = [(A, 0, B), (B, 0, C), (C, 2, T1), (T1, 0, T2), (T2, 1, A)]
+    rules = np.full((n, n), -1, dtype=np.int32)
+    for i in range(n):
+        rules[i, i] = 1
+        rules[i, (i + 1) % n] = 2
+    initial = [T1] + [A] * (n - 1)
+    return _net([5] * n, initial, [node] * n, 3, rules, f"token_ring_{n}")
+
+
+def random_lts(seed: int, n_procs: int, n_states, live, out_degree: int = 3,
+               n_labels: int = 32, rendezvous_frac: float = 0.25, sink_prob: float = 0.0,
+               name: str = "") -> Network:
+    """Random network of LTSs.
+
+    * labels 0 .. floor(rendezvous_frac * n_labels) - 1 are rendezvous labels,
+      each given a seeded pair (p, q), p != q, and the rule (label@p, label@q);
+      the other labels are local.
+    * process p declares ``n_states[p]`` states (the encoding width) of which
+      states 0 .. live[p]-1 are live; the initial state is 0.
+    * every live state other than 0 is a sink with probability ``sink_prob``;
+      every other live state gets ``out_degree`` transitions, each labelled with
+      one of p's rendezvous labels with probability ``rendezvous_frac`` (when p
+      has any) and with a uniform local label otherwise, and with a target
+      uniform over the live states.
+    """
+    rng = SplitMix64(seed)
+    ns = np.broadcast_to(np.asarray(n_states, dtype=np.int64), (n_procs,)).copy()
+    lv = np.broadcast_to(np.asarray(live, dtype=np.int64), (n_procs,)).copy()
+    lv = np.minimum(lv, ns)
+    n_rv = int(rendezvous_frac * n_labels) if n_procs >= 2 else 0
+    rules = np.full((n_rv, n_procs), -1, dtype=np.int32)
+    mine = [[] for _ in range(n_procs)]
+    for lab in range(n_rv):
+        p = rng.below(n_procs)
+        q = rng.below(n_procs - 1)
+        q = q + 1 if q >= p else q
+        rules[lab, p] = lab
+        rules[lab, q] = lab
+        mine[p].append(lab)
+        mine[q].append(lab)
+    trans = []
+    for p in range(n_procs):
+        rows = []
+        for s in range(int(lv[p])):
+            if s != 0 and sink_prob > 0 and rng.chance(sink_prob):
+                continue
+            for _ in range(out_degree):
+                if mine[p] and rng.chance(rendezvous_frac):
+                    lab = mine[p][rng.below(len(mine[p]))]
+                else:
+                    lab = n_rv + rng.below(n_labels - n_rv)
+                rows.append((s, lab, rng.below(int(lv[p]))))
+        trans.append(np.asarray(rows, dtype=np.uint32).reshape(-1, 3))
+    return _net(ns, [0] * n_procs, trans, n_labels, rules,
+                name or f"random_s{seed}_p{n_procs}", seed=seed, live=lv.tolist())
+
+
+# ------------------------------------------------------------- key streams
+MASK62 = (1 << 62) - 1
+
+
+def _mix62(x: np.ndarray) -> np.ndarray:
+    """A bijection of [0, 2^62): odd multiplies modulo 2^62 and xor-shifts."""
+    x = x.astype(np.uint64) & np.uint64(MASK62)
+    with np.errstate(over="ignore"):
+        x = (x * np.uint64(0x9FB21C651E98DF25)) & np.uint64(MASK62)
+        x ^= x >> np.uint64(29)
+        x = (x * np.uint64(0xD6E8FEB86659FD93)) & np.uint64(MASK62)
+        x ^= x >> np.uint64(32)
+        x = (x * np.uint64(0x94D049BB133111EB)) & np.uint64(MASK62)
+        x ^= x >> np.uint64(29)
+    return x
+
+
+def distinct_keys(n: int, w: int, seed: int) -> np.ndarray:
+    """n distinct keys of w words, every word with bit 31 clear.
+
+    Word 0 and word 1 come from a bijection of the counter i + seed over
+    [0, 2^62), so keys are distinct for n <= 2^62 when w >= 2 (for w == 1 the
+    counter itself, mixed over [0, 2^31), keeps them distinct for n <= 2^31).
+    Words 2 and 3 are further mixes of the same counter.
+    """
+    i = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        c = (i + np.uint64(seed & MASK62)) & np.uint64(MASK62)
+    out = np.empty((n, w), dtype=np.uint32)
+    if w == 1:
+        if n > (1 << 31):
+            raise ValueError("at most 2^31 distinct one-word keys")
+        x = c & np.uint64((1 << 31) - 1)
+        with np.errstate(over="ignore"):
+            x = (x * np.uint64(0x2545F491)) & np.uint64((1 << 31) - 1)
+            x ^= x >> np.uint64(15)
+            x = (x * np.uint64(0x6F4F2A35)) & np.uint64((1 << 31) - 1)
+            x ^= x >> np.uint64(13)
+        out[:, 0] = x.astype(np.uint32)
+        return out
+    x = _mix62(c)
+    out[:, 0] = (x & np.uint64(0x7FFFFFFF)).astype(np.uint32)
+    out[:, 1] = (x >> np.uint64(31)).astype(np.uint32)
+    if w >= 3:
+        y = _mix62(x ^ np.uint64(0x2AAAAAAAAAAAAAAA))
+        out[:, 2] = (y & np.uint64(0x7FFFFFFF)).astype(np.uint32)
+        if w == 4:
+            out[:, 3] = (y >> np.uint64(31)).astype(np.uint32)
+    return out
+
+
+def _permute_pow2(i: np.ndarray, bits: int, seed: int) -> np.ndarray:
+    """A seeded bijection of [0, 2^bits)."""
+    mask = np.uint64((1 << bits) - 1)
+    rng = SplitMix64(seed)
+    y = i.astype(np.uint64)
+    with np.errstate(over="ignore"):
+        for _ in range(3):
+            a = np.uint64(rng.next() | 1)
+            b = np.uint64(rng.next())
+            y = (y * a + b) & mask
+            y ^= y >> np.uint64(max(1, bits // 2))
+    return y
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    """A seeded permutation of [0, n) (bijection of the next power of two,
+    cycle-walked back into range)."""
+    if n <= 1:
+        return np.zeros(n, dtype=np.uint64)
+    bits = max(1, int(n - 1).bit_length())
+    y = _permute_pow2(np.arange(n, dtype=np.uint64), bits, seed)
+    bad = y >= np.uint64(n)
+    while bad.any():
+        y[bad] = _permute_pow2(y[bad], bits, seed)
+        bad = y >= np.uint64(n)
+    return y
+
+
+def duplicated_stream(n_distinct: int, dup: int, w: int, seed: int) -> np.ndarray:
+    """A stream of n_distinct * dup keys in which each of n_distinct distinct
+    keys occurs exactly ``dup`` times, in a seeded shuffled order (the key
+    streams of the isolated insert experiment of Sec. 5.1)."""
+    keys = distinct_keys(n_distinct, w, seed)
+    n = n_distinct * dup
+    order = permutation(n, seed ^ 0x5EED5EED5EED5EED)
+    return keys[(order % np.uint64(n_distinct)).astype(np.int64)]
