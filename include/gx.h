@@ -1,0 +1,273 @@
+/*
+ * gx.h -- C ABI of an MI355X (gfx950) library for GPUexplore-style
+ * explicit-state exploration and its bucketed find-or-put hash table,
+ * after Cassee, Neele and Wijs, "On the Scalability of the GPUexplore
+ * Explicit-State Model Checker" (GaM 2017, arXiv 1801.05857).
+ *
+ * Conventions for every call:
+ *   - Every function returns a gx_status; GX_OK (0) on success, a negative
+ *     code otherwise.  No exception crosses this boundary.
+ *   - Argument errors return GX_EINVAL before any device work is queued, and
+ *     leave every out-parameter untouched.
+ *   - Pointers documented as "device" must point to memory of the GPU that was
+ *     current when the table was created (e.g. a torch tensor's data_ptr()).
+ *     Pointers documented as "host" are ordinary process memory.
+ *   - A hip_stream argument is a hipStream_t passed as void*; NULL means the
+ *     null stream.  Calls documented as "stream-ordered" only enqueue work.
+ *   - Distinct tables are independent.  Concurrent gx_find_or_put calls on one
+ *     table are linearisable per key.  Other calls on one table must not
+ *     overlap with each other.
+ */
+#ifndef GX_H
+#define GX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GX_OK = 0,
+  GX_EINVAL = -1,     /* invalid argument, checked before any device work  */
+  GX_ENOMEM = -2,     /* device or host allocation failed, or a buffer of  */
+                      /* the call (frontier, deadlock list) was too small  */
+  GX_ETABLEFULL = -3, /* a key exhausted every hash function (Sec. 4.1)    */
+  GX_EDEVICE = -4,    /* a HIP runtime call failed                         */
+  GX_EBUSY = -5,
+  GX_ECANCELED = -6
+} gx_status;
+
+/* Per-key status byte written by gx_find_or_put. */
+enum {
+  GX_SEEN = 0,    /* the key was already stored                            */
+  GX_NEW = 1,     /* this call stored the key                              */
+  GX_FULL = 2,    /* every hash function led to a full bucket: not stored  */
+  GX_INVALID = 3  /* a word of the key equals GX_EMPTY_WORD: not stored    */
+};
+
+/* Value of an unused table word.  No key word may take this value. */
+#define GX_EMPTY_WORD 0xFFFFFFFFu
+
+/* Opaque handle; owns its device storage. */
+typedef struct gx_table gx_table;
+
+typedef struct {
+  uint64_t hash_seed;  /* seed of the hash-constant sets; 0 picks a fixed default */
+  uint32_t max_hashes; /* H, hash functions tried before a key is FULL; 0 -> 8      */
+  uint32_t subgroup;   /* lanes that probe one bucket: 8, 16, 32 or 64; 0 -> the
+                          smaller of bucket_words and 64                         */
+  uint32_t keys_per_subgroup; /* keys a subgroup keeps in flight: 1, 2 or 4;
+                                 0 -> 1                                          */
+  uint32_t reserved;
+} gx_table_opts;
+
+/*
+ * Create an empty table (Sec. 4.1: the storage is divided into buckets of
+ * bucket_words 32-bit integers; vectors are stored inline, i.e. closed
+ * hashing; Sec. 4.2: the bucket size is configurable).
+ *
+ *   words_per_state  w, 1..4.  Each key occupies a slot of S words, S = w for
+ *                    w in {1,2,4} and S = 4 for w = 3 (the fourth word is 0).
+ *   bucket_words     B, 8, 16, 32 or 64.  A bucket holds B/S slots.
+ *   capacity         number of keys the table must be able to hold; the table
+ *                    gets ceil(capacity / (B/S)) buckets (at least 1).
+ *   opts             nullable; see gx_table_opts.
+ *   out              receives the handle.
+ *
+ * The storage is allocated with hipMalloc on the current device and cleared
+ * (stream-ordered on the null stream, completed before return).
+ * Errors: GX_EINVAL (bad w, B, subgroup, keys_per_subgroup or H, capacity 0),
+ * GX_ENOMEM (allocation failed).
+ */
+gx_status gx_table_create(uint32_t words_per_state, uint32_t bucket_words, uint64_t capacity,
+                          const gx_table_opts* opts, gx_table** out);
+
+/* Free the table and its device storage.  NULL is accepted. */
+gx_status gx_table_destroy(gx_table* table);
+
+/* Reset every word to GX_EMPTY_WORD and the statistics to zero, with a fill
+ * kernel on hip_stream (stream-ordered). */
+gx_status gx_table_clear(gx_table* table, void* hip_stream);
+
+/*
+ * Find-or-put a batch of keys (Sec. 4.1 and 4.2): each key is looked up in the
+ * bucket given by the first hash function; if it is not there it is stored in
+ * the first free slot with a compare-and-swap; a bucket without a free slot
+ * sends the key to the bucket of the next hash function; after H full buckets
+ * the key is reported FULL and not stored.
+ *
+ *   keys     device, n * w uint32 words, row-major (key i = keys[i*w .. i*w+w)).
+ *   n        number of keys; 0 is accepted and does nothing.
+ *   status   device, n bytes; receives GX_NEW / GX_SEEN / GX_FULL / GX_INVALID
+ *            per key.  When a key occurs several times among keys that were
+ *            absent before the call, exactly one occurrence gets GX_NEW; which
+ *            one is unspecified.
+ *   n_new    device, nullable; when given, the number of GX_NEW keys is ADDED
+ *            to *n_new (the caller zeroes it).
+ *   hip_stream  stream-ordered; the call returns before the work completes.
+ *
+ * Errors: GX_EINVAL (null table/keys/status with n > 0), GX_EDEVICE (launch).
+ */
+gx_status gx_find_or_put(gx_table* table, const uint32_t* keys, uint64_t n, uint8_t* status,
+                         uint64_t* n_new, void* hip_stream);
+
+typedef struct {
+  uint32_t words_per_state; /* w */
+  uint32_t slot_words;      /* S */
+  uint32_t bucket_words;    /* B */
+  uint32_t subgroup;        /* lanes per bucket probe */
+  uint32_t keys_per_subgroup;
+  uint32_t max_hashes;      /* H */
+  uint64_t n_buckets;
+  uint64_t n_slots;         /* n_buckets * B / S */
+  uint64_t hash_seed;
+  uint64_t bytes;           /* device bytes of the bucket storage */
+} gx_table_info;
+
+/* Geometry of a table (host only, no device work). */
+gx_status gx_table_get_info(const gx_table* table, gx_table_info* out);
+
+typedef struct {
+  uint64_t stored;      /* keys stored since the last clear (GX_NEW results)   */
+  uint64_t lookups;     /* keys processed since the last clear                 */
+  uint64_t probes;      /* bucket reads (first reads and re-reads)             */
+  uint64_t full;        /* GX_FULL results                                     */
+  uint64_t invalid;     /* GX_INVALID results                                  */
+  uint32_t max_hash_index; /* largest hash index j used by a stored/found key */
+  uint32_t reserved;
+} gx_stats;
+
+/* Statistics since the last clear.  Waits for all device work to finish. */
+gx_status gx_table_stats(gx_table* table, gx_stats* out);
+
+/*
+ * Copy the stored keys to host memory, w words each, sorted lexicographically
+ * by (word0, word1, ...) as unsigned integers (slot padding removed).
+ * Waits for all device work.  *n_out receives the number of stored keys.  If
+ * host_keys is NULL or cap_states is smaller than that number, nothing is
+ * written to host_keys and GX_ENOMEM is returned (with *n_out set).
+ */
+gx_status gx_table_dump(gx_table* table, uint32_t* host_keys, uint64_t cap_states,
+                        uint64_t* n_out);
+
+/* Copy raw bucket storage words [first_word, first_word + n_words) to host
+ * memory (for placement checks).  Waits for all device work. */
+gx_status gx_table_read_raw(gx_table* table, uint32_t* host_words, uint64_t first_word,
+                            uint64_t n_words);
+
+/*
+ * Bucket index that hash function j assigns to a key (host only).  The family
+ * is h_j(k) = mulhi64(a_j * m(k) + c_j, n_buckets): m is a 64-bit mix of the
+ * key words under the seed, (a_j, c_j) the j-th set of hash constants drawn
+ * from the seed, and mulhi64 the high 64 bits of a 128-bit product (a range
+ * reduction that needs no power-of-two bucket count).  The paper fixes only
+ * that there are H sets of hash constants (8 by default, Sec. 4.1).
+ */
+gx_status gx_hash_bucket(const uint32_t* key, uint32_t words_per_state, uint64_t hash_seed,
+                         uint32_t j, uint64_t n_buckets, uint64_t* bucket);
+
+/* ------------------------------------------------------------ networks */
+
+/* One LTS (Sec. 3): n_states local states 0..n_states-1, an initial state and
+ * n_trans transitions (src[i], label[i], dst[i]), host arrays. */
+typedef struct {
+  uint32_t n_states, initial, n_trans;
+  const uint32_t* src;
+  const uint32_t* label;
+  const uint32_t* dst;
+} gx_lts;
+
+/*
+ * A network of LTSs with synchronisation rules (Sec. 3, Fig. 1).
+ * rules: host, n_rules x n_procs int32, row-major; entry [r][p] is the label
+ * process p must take in rule r, or -1 if p does not take part.  A transition
+ * of process p whose label is named at position p by some rule fires only
+ * through rules (all participants step together, one product transition per
+ * choice of matching transitions); every other transition fires alone.
+ */
+typedef struct {
+  uint32_t n_procs;
+  const gx_lts* procs;
+  uint32_t n_labels;
+  uint32_t n_rules;
+  const int32_t* rules;
+} gx_network;
+
+/*
+ * Words per packed state vector (Sec. 3: process states are combined in
+ * 32-bit integers; Sec. 5.2: longer vectors take several integers).  Field
+ * width of process p is max(1, ceil(log2 n_states)); fields are placed in
+ * process order from bit 0, a field that would cross bit 31 starts the next
+ * word, and bit 31 of every word stays 0.  Errors: GX_EINVAL for an invalid
+ * network or more than 4 words.
+ */
+gx_status gx_network_words(const gx_network* net, uint32_t* words_per_state);
+
+/* Pack n host vectors of local states (n x n_procs uint32) into n x w words
+ * (host only). */
+gx_status gx_network_pack(const gx_network* net, const uint32_t* local, uint64_t n,
+                          uint32_t* out);
+
+typedef struct {
+  uint64_t frontier_capacity; /* states per BFS frontier buffer; 0 -> the table's
+                                 slot count                                    */
+  uint64_t deadlock_capacity; /* deadlock states kept; 0 -> 1<<20              */
+  void* hip_stream;           /* stream for every launch of the call           */
+  uint32_t reserved[4];
+} gx_explore_opts;
+
+typedef struct {
+  uint64_t n_states;      /* reachable states                                  */
+  uint64_t n_transitions; /* product transitions of the reachable states       */
+  uint32_t words_per_state;
+  uint32_t n_levels;      /* BFS levels; level 0 is the initial state          */
+  uint64_t* level_counts; /* n_levels entries (library-owned)                  */
+  uint64_t n_deadlocks;   /* reachable states without a product transition     */
+  uint32_t* deadlocks;    /* n_deadlocks x w words, sorted (library-owned)     */
+} gx_explore_result;
+
+/*
+ * Breadth-first exploration of the synchronous product (Sec. 3), level by
+ * level, with on-the-fly deadlock detection.  Every successor goes through
+ * the table's find-or-put; states it reports NEW form the next level.
+ *
+ *   net    host description; compiled to a device image for the call.
+ *   table  caller-created, empty, with words_per_state equal to
+ *          gx_network_words(net); it holds the reachable set afterwards.
+ *   opts   nullable.
+ *   out    filled on success; free with gx_explore_result_free.
+ *
+ * Synchronous: returns when the exploration ends.
+ * Errors: GX_EINVAL (invalid network, word count mismatch, non-empty table,
+ * network image too large for the kernel's LDS), GX_ETABLEFULL (a state
+ * exhausted every hash function; exploration stops, no result), GX_ENOMEM
+ * (frontier or deadlock buffer too small, or allocation failure).
+ */
+gx_status gx_explore(const gx_network* net, gx_table* table, const gx_explore_opts* opts,
+                     gx_explore_result* out);
+
+/* Release the arrays of a result filled by gx_explore.  NULL is accepted. */
+void gx_explore_result_free(gx_explore_result* result);
+
+/* Static string naming a status code. */
+const char* gx_status_str(gx_status status);
+
+/* ------------------------------------------------------------ measurement */
+
+/*
+ * Random-access bandwidth probe: n_reads reads of `granule` bytes (4..256,
+ * power of two) at pseudo-random granule-aligned offsets of a device buffer of
+ * buf_bytes bytes (buf_bytes >= granule), one subgroup of granule/4 lanes (at
+ * most 64) per read; the sum of the values read is written to *sink (device,
+ * 8 bytes) so the reads cannot be removed.  Stream-ordered.  Gives the
+ * achievable random-access bandwidth that bounds the table probes.
+ */
+gx_status gx_gather_probe(const uint32_t* buf, uint64_t buf_bytes, uint32_t granule,
+                          uint64_t n_reads, uint64_t seed, uint64_t* sink, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GX_H */

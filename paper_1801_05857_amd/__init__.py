@@ -1,0 +1,349 @@
+"""Python binding of ``libgx.so`` (declared in include/gx.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors (their ``data_ptr()``), streams are
+torch streams (their ``cuda_stream`` handle); when no stream is given the
+current torch stream is used, so work is ordered with the caller's torch ops.
+
+There is no fallback: if ``libgx.so`` is missing every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgx.so")
+
+# status codes (gx_status)
+GX_OK, GX_EINVAL, GX_ENOMEM, GX_ETABLEFULL, GX_EDEVICE, GX_EBUSY, GX_ECANCELED = (
+    0, -1, -2, -3, -4, -5, -6)
+# per-key status bytes
+GX_SEEN, GX_NEW, GX_FULL, GX_INVALID = 0, 1, 2, 3
+EMPTY_WORD = 0xFFFFFFFF
+
+EXPORTED = [
+    "gx_table_create", "gx_table_destroy", "gx_table_clear", "gx_find_or_put",
+    "gx_table_get_info", "gx_table_stats", "gx_table_dump", "gx_table_read_raw",
+    "gx_hash_bucket", "gx_network_words", "gx_network_pack", "gx_explore",
+    "gx_explore_result_free", "gx_status_str", "gx_gather_probe",
+]
+
+
+class GxError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+
+
+class _TableOpts(ctypes.Structure):
+    _fields_ = [("hash_seed", ctypes.c_uint64), ("max_hashes", ctypes.c_uint32),
+                ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class _TableInfo(ctypes.Structure):
+    _fields_ = [("words_per_state", ctypes.c_uint32), ("slot_words", ctypes.c_uint32),
+                ("bucket_words", ctypes.c_uint32), ("subgroup", ctypes.c_uint32),
+                ("keys_per_subgroup", ctypes.c_uint32), ("max_hashes", ctypes.c_uint32),
+                ("n_buckets", ctypes.c_uint64), ("n_slots", ctypes.c_uint64),
+                ("hash_seed", ctypes.c_uint64), ("bytes", ctypes.c_uint64)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("stored", ctypes.c_uint64), ("lookups", ctypes.c_uint64),
+                ("probes", ctypes.c_uint64), ("full", ctypes.c_uint64),
+                ("invalid", ctypes.c_uint64), ("max_hash_index", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class _Lts(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_uint32), ("initial", ctypes.c_uint32),
+                ("n_trans", ctypes.c_uint32), ("src", ctypes.c_void_p),
+                ("label", ctypes.c_void_p), ("dst", ctypes.c_void_p)]
+
+
+class _Network(ctypes.Structure):
+    _fields_ = [("n_procs", ctypes.c_uint32), ("procs", ctypes.POINTER(_Lts)),
+                ("n_labels", ctypes.c_uint32), ("n_rules", ctypes.c_uint32),
+                ("rules", ctypes.c_void_p)]
+
+
+class _ExploreOpts(ctypes.Structure):
+    _fields_ = [("frontier_capacity", ctypes.c_uint64), ("deadlock_capacity", ctypes.c_uint64),
+                ("hip_stream", ctypes.c_void_p), ("reserved", ctypes.c_uint32 * 4)]
+
+
+class _ExploreResult(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_uint64), ("n_transitions", ctypes.c_uint64),
+                ("words_per_state", ctypes.c_uint32), ("n_levels", ctypes.c_uint32),
+                ("level_counts", ctypes.POINTER(ctypes.c_uint64)),
+                ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32))]
+
+
+_lib_handle = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                "g.build()'` (or paper_1801_05857_amd/build.py); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        st, vp, u32, u64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        L.gx_table_create.restype = st
+        L.gx_table_create.argtypes = [u32, u32, u64, ctypes.POINTER(_TableOpts),
+                                      ctypes.POINTER(vp)]
+        L.gx_table_destroy.restype = st
+        L.gx_table_destroy.argtypes = [vp]
+        L.gx_table_clear.restype = st
+        L.gx_table_clear.argtypes = [vp, vp]
+        L.gx_find_or_put.restype = st
+        L.gx_find_or_put.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.gx_table_get_info.restype = st
+        L.gx_table_get_info.argtypes = [vp, ctypes.POINTER(_TableInfo)]
+        L.gx_table_stats.restype = st
+        L.gx_table_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.gx_table_dump.restype = st
+        L.gx_table_dump.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
+        L.gx_table_read_raw.restype = st
+        L.gx_table_read_raw.argtypes = [vp, vp, u64, u64]
+        L.gx_hash_bucket.restype = st
+        L.gx_hash_bucket.argtypes = [vp, u32, u64, u32, u64, ctypes.POINTER(u64)]
+        L.gx_network_words.restype = st
+        L.gx_network_words.argtypes = [ctypes.POINTER(_Network), ctypes.POINTER(u32)]
+        L.gx_network_pack.restype = st
+        L.gx_network_pack.argtypes = [ctypes.POINTER(_Network), vp, u64, vp]
+        L.gx_explore.restype = st
+        L.gx_explore.argtypes = [ctypes.POINTER(_Network), vp, ctypes.POINTER(_ExploreOpts),
+                                 ctypes.POINTER(_ExploreResult)]
+        L.gx_explore_result_free.restype = None
+        L.gx_explore_result_free.argtypes = [ctypes.POINTER(_ExploreResult)]
+        L.gx_status_str.restype = ctypes.c_char_p
+        L.gx_status_str.argtypes = [st]
+        L.gx_gather_probe.restype = st
+        L.gx_gather_probe.argtypes = [vp, u64, u32, u64, u64, vp, vp]
+        _lib_handle = L
+    return _lib_handle
+
+
+def status_str(code: int) -> str:
+    return lib().gx_status_str(code).decode()
+
+
+def _check(code: int, what: str) -> None:
+    if code != GX_OK:
+        raise GxError(code, what)
+
+
+def _stream_handle(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(getattr(stream, "cuda_stream", stream) or 0)
+
+
+def _dev_ptr(t, what: str) -> int:
+    if t is None:
+        return 0
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return int(t.data_ptr())
+
+
+# ------------------------------------------------------------------ table
+@dataclass
+class TableInfo:
+    words_per_state: int
+    slot_words: int
+    bucket_words: int
+    subgroup: int
+    keys_per_subgroup: int
+    max_hashes: int
+    n_buckets: int
+    n_slots: int
+    hash_seed: int
+    bytes: int
+
+
+@dataclass
+class Stats:
+    stored: int
+    lookups: int
+    probes: int
+    full: int
+    invalid: int
+    max_hash_index: int
+
+
+class Table:
+    """gx_table: a bucketed find-or-put table in device memory."""
+
+    def __init__(self, words_per_state: int, bucket_words: int, capacity: int, *,
+                 hash_seed: int = 0, max_hashes: int = 0, subgroup: int = 0,
+                 keys_per_subgroup: int = 0):
+        opts = _TableOpts(hash_seed, max_hashes, subgroup, keys_per_subgroup, 0)
+        h = ctypes.c_void_p()
+        _check(lib().gx_table_create(words_per_state, bucket_words, capacity,
+                                     ctypes.byref(opts), ctypes.byref(h)), "gx_table_create")
+        self._h = h
+        self.info = self._info()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("table destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().gx_table_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _info(self) -> TableInfo:
+        i = _TableInfo()
+        _check(lib().gx_table_get_info(self.handle, ctypes.byref(i)), "gx_table_get_info")
+        return TableInfo(i.words_per_state, i.slot_words, i.bucket_words, i.subgroup,
+                         i.keys_per_subgroup, i.max_hashes, i.n_buckets, i.n_slots,
+                         i.hash_seed, i.bytes)
+
+    def clear(self, stream=None) -> None:
+        _check(lib().gx_table_clear(self.handle, _stream_handle(stream)), "gx_table_clear")
+
+    def find_or_put(self, keys, status, n_new=None, stream=None) -> None:
+        """keys: device int32/uint32 tensor (n, w); status: device uint8 (n,);
+        n_new: optional device int64 (1,) to which the NEW count is added."""
+        n = keys.shape[0] if keys.dim() > 0 else 0
+        if keys.dim() != 2 or keys.shape[1] != self.info.words_per_state:
+            raise ValueError("keys must have shape (n, words_per_state)")
+        if status.numel() < n:
+            raise ValueError("status too small")
+        _check(lib().gx_find_or_put(self.handle, _dev_ptr(keys, "keys"), n,
+                                    _dev_ptr(status, "status"), _dev_ptr(n_new, "n_new"),
+                                    _stream_handle(stream)), "gx_find_or_put")
+
+    def stats(self) -> Stats:
+        s = _Stats()
+        _check(lib().gx_table_stats(self.handle, ctypes.byref(s)), "gx_table_stats")
+        return Stats(s.stored, s.lookups, s.probes, s.full, s.invalid, s.max_hash_index)
+
+    def dump(self) -> np.ndarray:
+        """Stored keys, sorted lexicographically, shape (n, w) uint32."""
+        n = ctypes.c_uint64()
+        code = lib().gx_table_dump(self.handle, None, 0, ctypes.byref(n))
+        if code not in (GX_OK, GX_ENOMEM):
+            _check(code, "gx_table_dump")
+        out = np.empty((n.value, self.info.words_per_state), dtype=np.uint32)
+        _check(lib().gx_table_dump(self.handle, out.ctypes.data, n.value, ctypes.byref(n)),
+               "gx_table_dump")
+        return out
+
+    def read_raw(self, first_word: int = 0, n_words: int | None = None) -> np.ndarray:
+        total = self.info.n_buckets * self.info.bucket_words
+        if n_words is None:
+            n_words = total - first_word
+        out = np.empty(n_words, dtype=np.uint32)
+        _check(lib().gx_table_read_raw(self.handle, out.ctypes.data, first_word, n_words),
+               "gx_table_read_raw")
+        return out
+
+
+def hash_bucket(key, words_per_state: int, hash_seed: int, j: int, n_buckets: int) -> int:
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1)
+    out = ctypes.c_uint64()
+    _check(lib().gx_hash_bucket(k.ctypes.data, words_per_state, hash_seed, j, n_buckets,
+                                ctypes.byref(out)), "gx_hash_bucket")
+    return int(out.value)
+
+
+# ------------------------------------------------------------------ networks
+class _NetHolder:
+    """ctypes view of a network object (n_states, initial, trans, n_labels,
+    rules); keeps the arrays alive while the library reads them."""
+
+    def __init__(self, net):
+        P = len(net.n_states)
+        self.arrays = []
+        procs = (_Lts * P)()
+        for p in range(P):
+            t = np.ascontiguousarray(np.asarray(net.trans[p], dtype=np.uint32).reshape(-1, 3))
+            src, lab, dst = (np.ascontiguousarray(t[:, i]) for i in range(3))
+            self.arrays += [src, lab, dst]
+            procs[p] = _Lts(int(net.n_states[p]), int(net.initial[p]), t.shape[0],
+                            src.ctypes.data, lab.ctypes.data, dst.ctypes.data)
+        rules = np.ascontiguousarray(np.asarray(net.rules, dtype=np.int32).reshape(-1, P))
+        self.arrays += [rules, procs]
+        self.c = _Network(P, procs, int(net.n_labels), rules.shape[0],
+                          rules.ctypes.data if rules.size else None)
+
+
+def network_words(net) -> int:
+    h = _NetHolder(net)
+    w = ctypes.c_uint32()
+    _check(lib().gx_network_words(ctypes.byref(h.c), ctypes.byref(w)), "gx_network_words")
+    return int(w.value)
+
+
+def network_pack(net, local) -> np.ndarray:
+    h = _NetHolder(net)
+    P = len(net.n_states)
+    loc = np.ascontiguousarray(local, dtype=np.uint32).reshape(-1, P)
+    w = network_words(net)
+    out = np.empty((loc.shape[0], w), dtype=np.uint32)
+    _check(lib().gx_network_pack(ctypes.byref(h.c), loc.ctypes.data, loc.shape[0],
+                                 out.ctypes.data), "gx_network_pack")
+    return out
+
+
+@dataclass
+class ExploreResult:
+    n_states: int
+    n_transitions: int
+    words_per_state: int
+    levels: np.ndarray
+    deadlocks: np.ndarray
+
+
+def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity: int = 0,
+            stream=None) -> ExploreResult:
+    """gx_explore: BFS of the synchronous product into ``table``."""
+    h = _NetHolder(net)
+    opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream))
+    res = _ExploreResult()
+    _check(lib().gx_explore(ctypes.byref(h.c), table.handle, ctypes.byref(opts),
+                            ctypes.byref(res)), "gx_explore")
+    try:
+        w = res.words_per_state
+        levels = np.ctypeslib.as_array(res.level_counts, shape=(res.n_levels,)).copy()
+        if res.n_deadlocks:
+            dead = np.ctypeslib.as_array(res.deadlocks, shape=(res.n_deadlocks * w,)).copy()
+        else:
+            dead = np.zeros(0, np.uint32)
+        return ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
+                             dead.reshape(-1, w))
+    finally:
+        lib().gx_explore_result_free(ctypes.byref(res))
+
+
+def gather_probe(buf, granule: int, n_reads: int, seed: int, sink, stream=None) -> None:
+    """gx_gather_probe over a device tensor ``buf``; ``sink``: device int64 (1,)."""
+    _check(lib().gx_gather_probe(_dev_ptr(buf, "buf"), buf.numel() * buf.element_size(),
+                                 granule, n_reads, seed, _dev_ptr(sink, "sink"),
+                                 _stream_handle(stream)), "gx_gather_probe")

@@ -1,0 +1,450 @@
+// Device core of the bucketed find-or-put table (Sec. 4.1 and 4.2 of
+// "On the Scalability of the GPUexplore Explicit-State Model Checker").
+//
+// Table layout: n_buckets buckets of B 32-bit words, bucket b at words
+// [b*B, b*B + B).  A key of w words lives in a slot of S words (S = w, or 4
+// for w = 3 with the fourth word 0); a bucket holds B/S slots, slot s at
+// bucket words [s*S, s*S + S).  Unused words hold kEmpty.  No key word may be
+// kEmpty, so a slot is EMPTY (every word kEmpty), FINAL (no word kEmpty) or,
+// transiently, PARTIAL.
+//
+// Probe (one subgroup of G lanes per key, G in {8,16,32,64}; the paper uses a
+// warp of 32 per bucket of 32 integers, and groups of B threads for buckets of
+// B integers, Sec. 4.2):
+//   * the first GE = min(G, B) lanes each load K = B/GE consecutive words of
+//     the bucket (one coalesced access of B*4 bytes per bucket);
+//   * every lane compares its words with the key; ballots give per-slot
+//     "match", "empty" and "partial" masks for the subgroup;
+//   * match -> SEEN.  Otherwise the lane owning the lowest EMPTY slot tries a
+//     compare-and-swap of the key into it (32-bit for S = 1, 64-bit for S = 2,
+//     64-bit on words 0-1 for S = 4 followed by a store of words 2-3); a
+//     failed CAS that returned the key -> SEEN, any other failure -> re-read
+//     the bucket; no EMPTY slot -> next hash function (Sec. 4.1); after H
+//     buckets -> FULL.
+//
+// Memory-model argument (why relaxed atomics are enough): every slot word is
+// written exactly once, from kEmpty to its final value, and no reader derives
+// anything from a slot except by comparing its words with a key.  A stale
+// kEmpty from a plain load only costs a failed CAS, whose returned value is
+// compared; a non-kEmpty value is final.  A PARTIAL slot (a head claimed and
+// its tail not yet stored, or a torn read of a 64-bit slot) blocks claiming in
+// its bucket until a re-read, done with agent-scope atomic loads, shows it
+// EMPTY or FINAL.  Every inserter visits buckets in the same h_0, h_1, ...
+// order and claims only the lowest EMPTY slot after comparing every FINAL
+// slot, so a key is never stored twice.
+//
+// Forward progress: a lane that wins a head CAS stores the tail in the same
+// straight-line step; waiting for someone else's tail is never a spin inside a
+// branch but another pass of the outer loop, so lanes of one wavefront cannot
+// wait on each other.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gx {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+enum : uint8_t { kSeen = 0, kNew = 1, kFull = 2, kInvalid = 3 };
+
+// SplitMix64 output function (Steele, Lea, Flood 2014).
+__host__ __device__ inline uint64_t fmix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+  return static_cast<uint64_t>((static_cast<unsigned __int128>(a) * b) >> 64);
+}
+
+// 64-bit mix of a slot-format key (S words, the padding word of a 3-word key
+// is 0) under the table seed.
+template <int S>
+__host__ __device__ inline uint64_t key_mix(const uint32_t (&k)[S], uint64_t seed) {
+  uint64_t x = k[0];
+  if constexpr (S >= 2) x |= static_cast<uint64_t>(k[1]) << 32;
+  if constexpr (S == 4) {
+    x = fmix64(x ^ seed) ^ (static_cast<uint64_t>(k[2]) | (static_cast<uint64_t>(k[3]) << 32));
+  }
+  return fmix64(x ^ seed);
+}
+
+// j-th set of hash constants (a_j odd, c_j) drawn from the seed.
+__host__ __device__ inline void hash_constants(uint64_t seed, uint32_t j, uint64_t* a,
+                                               uint64_t* c) {
+  *a = fmix64(seed + (2ull * j + 1ull) * kGolden) | 1ull;
+  *c = fmix64(seed + (2ull * j + 2ull) * kGolden);
+}
+
+__host__ __device__ inline uint64_t bucket_of(uint64_t mix, uint64_t a, uint64_t c,
+                                              uint64_t n_buckets) {
+  return mulhi64(a * mix + c, n_buckets);
+}
+
+// Counters kept with every table (one u64 each).
+enum Counter : int {
+  kCntStored = 0,
+  kCntLookups = 1,
+  kCntProbes = 2,
+  kCntFull = 3,
+  kCntInvalid = 4,
+  kCntMaxJ = 5,
+  kNumCounters = 8
+};
+
+struct TableDev {
+  uint32_t* words;
+  uint64_t n_buckets;
+  const uint64_t* hc;  // 2*H hash constants: a_0, c_0, a_1, c_1, ...
+  uint64_t seed;
+  uint64_t a0, c0;     // first constant set, passed by value
+  uint32_t H;
+  uint64_t* counters;  // kNumCounters
+};
+
+template <int S, int B, int G>
+struct Geo {
+  static_assert(S == 1 || S == 2 || S == 4, "slot words");
+  static_assert(B == 8 || B == 16 || B == 32 || B == 64, "bucket words");
+  static_assert(G == 8 || G == 16 || G == 32 || G == 64, "subgroup width");
+  static constexpr int GE = G < B ? G : B;          // lanes holding bucket words
+  static constexpr int K = B / GE;                  // words per lane
+  static constexpr int L = K >= S ? 1 : S / K;      // lanes per slot
+  static constexpr int SPL = K >= S ? K / S : 1;    // whole slots per lane
+  static constexpr int SUBS = 64 / G;               // subgroups per wavefront
+  static constexpr uint64_t GMASK = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  // bits 0, L, 2L, ... below GE
+  static constexpr uint64_t lead_mask() {
+    uint64_t m = 0;
+    for (int i = 0; i < GE; i += L) m |= 1ull << i;
+    return m;
+  }
+};
+
+template <int K>
+__device__ inline void load_view(const uint32_t* p, uint32_t (&v)[K]) {
+  if constexpr (K == 1) {
+    v[0] = p[0];
+  } else if constexpr (K == 2) {
+    uint2 t = *reinterpret_cast<const uint2*>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+  } else if constexpr (K == 4) {
+    uint4 t = *reinterpret_cast<const uint4*>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+  } else {
+    static_assert(K == 8, "words per lane");
+    uint4 t0 = reinterpret_cast<const uint4*>(p)[0];
+    uint4 t1 = reinterpret_cast<const uint4*>(p)[1];
+    v[0] = t0.x;
+    v[1] = t0.y;
+    v[2] = t0.z;
+    v[3] = t0.w;
+    v[4] = t1.x;
+    v[5] = t1.y;
+    v[6] = t1.z;
+    v[7] = t1.w;
+  }
+}
+
+// Re-read with agent-scope atomic loads: never served from a stale cache line.
+template <int K>
+__device__ inline void load_view_fresh(uint32_t* p, uint32_t (&v)[K]) {
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    v[t] = __hip_atomic_load(p + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// k[idx] for a run-time idx, with mask arithmetic (see get_field in the
+// exploration kernel: a select chain becomes a private-array indexed load).
+template <int S>
+__device__ __forceinline__ uint32_t key_word(const uint32_t (&k)[S], int idx) {
+  uint32_t x = 0;
+#pragma unroll
+  for (int t = 0; t < S; ++t) x |= k[t] & (0u - static_cast<uint32_t>(idx == t));
+  return x;
+}
+
+// Result of comparing one bucket view with a key, uniform over a subgroup.
+struct Eval {
+  bool match;     // a FINAL slot equals the key
+  bool partial;   // some slot is PARTIAL
+  int claim_lane; // lane (within the subgroup) owning the lowest EMPTY slot, -1 if none
+  int claim_word; // on the claiming lane: offset of that slot within the lane's words
+};
+
+template <int S, int B, int G>
+__device__ inline Eval evaluate(const uint32_t (&v)[Geo<S, B, G>::K], const uint32_t (&key)[S],
+                                int li, int shift) {
+  using Gm = Geo<S, B, G>;
+  constexpr int K = Gm::K;
+  Eval ev;
+  if constexpr (Gm::L == 1) {
+    uint32_t em = 0;
+    bool mt = false, pt = false;
+    if (li < Gm::GE) {
+#pragma unroll
+      for (int s = 0; s < Gm::SPL; ++s) {
+        bool alle = true, alln = true, eq = true;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          uint32_t x = v[s * S + t];
+          alle &= (x == kEmpty);
+          alln &= (x != kEmpty);
+          eq &= (x == key[t]);
+        }
+        em |= static_cast<uint32_t>(alle) << s;
+        mt |= alln && eq;
+        pt |= !alle && !alln;
+      }
+    }
+    const uint64_t M = (__ballot(mt) >> shift) & Gm::GMASK;
+    const uint64_t P = (__ballot(pt) >> shift) & Gm::GMASK;
+    const uint64_t E = (__ballot(em != 0) >> shift) & Gm::GMASK;
+    ev.match = M != 0;
+    ev.partial = P != 0;
+    ev.claim_lane = E ? (__ffsll(static_cast<unsigned long long>(E)) - 1) : -1;
+    ev.claim_word = em ? (__ffs(em) - 1) * S : 0;
+  } else {
+    constexpr int L = Gm::L;
+    bool fe = false, ff = false, fq = false;
+    if (li < Gm::GE) {
+      fe = true;
+      ff = true;
+      fq = true;
+      const int off = (li % L) * K;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        uint32_t x = v[t];
+        fe &= (x == kEmpty);
+        ff &= (x != kEmpty);
+        fq &= (x == key_word<S>(key, off + t));
+      }
+    }
+    const uint64_t E = (__ballot(fe) >> shift) & Gm::GMASK;
+    const uint64_t F = (__ballot(ff) >> shift) & Gm::GMASK;
+    const uint64_t Q = (__ballot(fq && ff) >> shift) & Gm::GMASK;
+    uint64_t ae = E, af = F, aq = Q;
+#pragma unroll
+    for (int d = 1; d < L; ++d) {
+      ae &= E >> d;
+      af &= F >> d;
+      aq &= Q >> d;
+    }
+    constexpr uint64_t lead = Gm::lead_mask();
+    ae &= lead;
+    af &= lead;
+    aq &= lead;
+    ev.match = aq != 0;
+    ev.partial = (ae | af) != lead;
+    ev.claim_lane = ae ? (__ffsll(static_cast<unsigned long long>(ae)) - 1) : -1;
+    ev.claim_word = 0;
+  }
+  return ev;
+}
+
+// Per-lane statistics, reduced once per wavefront at kernel end.
+struct LaneStats {
+  uint32_t stored = 0, lookups = 0, probes = 0, full = 0, invalid = 0, max_j = 0;
+};
+
+__device__ inline uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+__device__ inline uint32_t wave_max(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint32_t y = __shfl_xor(x, d, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+__device__ inline void flush_stats(const TableDev& t, const LaneStats& st, uint64_t* n_new) {
+  const uint32_t stored = wave_sum(st.stored);
+  const uint32_t lookups = wave_sum(st.lookups);
+  const uint32_t probes = wave_sum(st.probes);
+  const uint32_t full = wave_sum(st.full);
+  const uint32_t invalid = wave_sum(st.invalid);
+  const uint32_t mj = wave_max(st.max_j);
+  if (__lane_id() == 0) {
+    if (stored) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntStored]), stored);
+      if (n_new) atomicAdd(reinterpret_cast<unsigned long long*>(n_new), stored);
+    }
+    if (lookups) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntLookups]), lookups);
+    if (probes) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntProbes]), probes);
+    if (full) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntFull]), full);
+    if (invalid) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntInvalid]), invalid);
+    if (mj) atomicMax(reinterpret_cast<unsigned long long*>(&t.counters[kCntMaxJ]), mj);
+  }
+}
+
+// Find-or-put of U keys per subgroup (every lane of a subgroup holds the same
+// keys).  act[u] false: no key.  On return res[u] holds kNew / kSeen / kFull /
+// kInvalid for active keys; hash index used in jres[u].  The call must be
+// reached by the whole wavefront (it ballots across it).
+template <int S, int B, int G, int U>
+__device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S],
+                                   const bool (&act_in)[U], uint8_t (&res)[U], LaneStats& st) {
+  using Gm = Geo<S, B, G>;
+  constexpr int K = Gm::K;
+  const int lane = __lane_id();
+  const int li = lane % G;
+  const int shift = (lane / G) * G;
+
+  bool act[U];
+  uint32_t j[U];
+  uint64_t mix[U];
+  uint64_t bkt[U];
+  uint32_t view[U][K];
+
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    act[u] = act_in[u];
+    res[u] = kSeen;
+    j[u] = 0;
+    bool bad = false;
+#pragma unroll
+    for (int w = 0; w < S; ++w) bad |= key[u][w] == kEmpty;
+    if (act[u] && bad) {
+      res[u] = kInvalid;
+      act[u] = false;
+      if (li == 0) ++st.invalid;
+    }
+    if (act[u] && li == 0) ++st.lookups;
+    mix[u] = key_mix<S>(key[u], t.seed);
+    bkt[u] = bucket_of(mix[u], t.a0, t.c0, t.n_buckets);
+#pragma unroll
+    for (int w = 0; w < K; ++w) view[u][w] = kEmpty;
+    if (act[u]) {
+      if (li < Gm::GE) load_view<K>(t.words + bkt[u] * B + li * K, view[u]);
+      if (li == 0) ++st.probes;
+    }
+  }
+
+  while (true) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) any |= act[u];
+    if (!__any(any)) break;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!act[u]) continue;
+      const Eval ev = evaluate<S, B, G>(view[u], key[u], li, shift);
+      uint32_t* const base = t.words + bkt[u] * B + li * K;
+      bool reread = false;
+      if (ev.match) {
+        res[u] = kSeen;
+        act[u] = false;
+      } else if (ev.partial) {
+        reread = true;
+      } else if (ev.claim_lane >= 0) {
+        bool won = false, same = false;
+        // the slot value the CAS observed (claiming lane only)
+        uint32_t o0 = kEmpty, o1 = kEmpty, o2 = kEmpty, o3 = kEmpty;
+        if (li == ev.claim_lane) {
+          uint32_t* slot = base + ev.claim_word;
+          if constexpr (S == 1) {
+            uint32_t exp = kEmpty;
+            won = __hip_atomic_compare_exchange_strong(slot, &exp, key[u][0], __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            same = !won && exp == key[u][0];
+            o0 = exp;
+          } else {
+            const uint64_t head =
+                static_cast<uint64_t>(key[u][0]) | (static_cast<uint64_t>(key[u][1]) << 32);
+            uint64_t exp = ~0ull;
+            won = __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t*>(slot), &exp,
+                                                       head, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            o0 = static_cast<uint32_t>(exp);
+            o1 = static_cast<uint32_t>(exp >> 32);
+            if constexpr (S == 2) {
+              same = !won && exp == head;
+            } else {
+              const uint64_t tail =
+                  static_cast<uint64_t>(key[u][2]) | (static_cast<uint64_t>(key[u][3]) << 32);
+              if (won) {
+                __hip_atomic_store(reinterpret_cast<uint64_t*>(slot + 2), tail, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+              } else if (exp == head) {
+                // same head: the tail decides (still kEmpty while its owner
+                // has not stored it, which leaves the slot PARTIAL)
+                const uint64_t got =
+                    __hip_atomic_load(reinterpret_cast<uint64_t*>(slot + 2), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                same = got == tail;
+                o2 = static_cast<uint32_t>(got);
+                o3 = static_cast<uint32_t>(got >> 32);
+              } else {
+                // another key's head: the slot can never match, its tail is
+                // irrelevant (any non-kEmpty placeholder keeps it FINAL)
+                o2 = 0;
+                o3 = 0;
+              }
+            }
+          }
+        }
+        const uint64_t W = (__ballot(won) >> shift) & Gm::GMASK;
+        const uint64_t Sm = (__ballot(same) >> shift) & Gm::GMASK;
+        if (W) {
+          res[u] = kNew;
+          act[u] = false;
+          if (li == 0) ++st.stored;
+        } else if (Sm) {
+          res[u] = kSeen;
+          act[u] = false;
+        } else {
+          // Patch the view with what the CAS saw: that slot is no longer a
+          // candidate, so every failed CAS retires one slot for good and the
+          // loop makes progress whatever the plain loads returned.
+          const int src = shift + ev.claim_lane;
+          const uint32_t s0 = __shfl(o0, src, 64);
+          const uint32_t s1 = __shfl(o1, src, 64);
+          const uint32_t s2 = __shfl(o2, src, 64);
+          const uint32_t s3 = __shfl(o3, src, 64);
+          const int cw = ev.claim_lane * K + __shfl(ev.claim_word, src, 64);
+          const uint32_t sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+          for (int x = 0; x < K; ++x) {
+            const int d = li * K + x - cw;
+            if (li < Gm::GE && d >= 0 && d < S) view[u][x] = key_word<4>(sv, d);
+          }
+        }
+      } else {
+        // bucket full of other keys: next set of hash constants
+        ++j[u];
+        if (j[u] >= t.H) {
+          res[u] = kFull;
+          act[u] = false;
+          if (li == 0) ++st.full;
+        } else {
+          const uint64_t a = t.hc[2 * j[u]], c = t.hc[2 * j[u] + 1];
+          bkt[u] = bucket_of(mix[u], a, c, t.n_buckets);
+          if (li < Gm::GE) load_view<K>(t.words + bkt[u] * B + li * K, view[u]);
+          if (li == 0) ++st.probes;
+        }
+      }
+      if (reread) {
+        if (li < Gm::GE) load_view_fresh<K>(base, view[u]);
+        if (li == 0) ++st.probes;
+      }
+      if (!act[u] && li == 0 && res[u] != kFull && j[u] > st.max_j) st.max_j = j[u];
+    }
+  }
+}
+
+}  // namespace gx

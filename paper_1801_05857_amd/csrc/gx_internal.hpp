@@ -1,0 +1,51 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/gx.h"
+#include "gx_device.hpp"
+
+struct gx_table {
+  int device = 0;
+  uint32_t w = 0;  // words per state
+  uint32_t S = 0;  // slot words
+  uint32_t B = 0;  // bucket words
+  uint32_t G = 0;  // subgroup width
+  uint32_t U = 1;  // keys in flight per subgroup
+  uint32_t H = 8;  // hash functions
+  uint64_t seed = 0;
+  uint64_t n_buckets = 0;
+  uint32_t* words = nullptr;     // n_buckets * B
+  uint64_t* hc = nullptr;        // 2*H hash constants
+  uint64_t* counters = nullptr;  // gx::kNumCounters
+  uint64_t a0 = 0, c0 = 0;
+
+  gx::TableDev dev() const {
+    gx::TableDev t;
+    t.words = words;
+    t.n_buckets = n_buckets;
+    t.hc = hc;
+    t.seed = seed;
+    t.a0 = a0;
+    t.c0 = c0;
+    t.H = H;
+    t.counters = counters;
+    return t;
+  }
+};
+
+namespace gx {
+
+inline uint32_t slot_words(uint32_t w) { return w == 3 ? 4u : w; }
+
+// Launch the find-or-put kernel specialised for the table's (S, B, G, U).
+hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t n,
+                              uint8_t* status, uint64_t* n_new, hipStream_t stream);
+
+// Number of workgroups that keep every CU busy for a grid-stride kernel.
+uint32_t resident_grid(int device, uint32_t per_cu);
+
+}  // namespace gx

@@ -1,0 +1,466 @@
+// Bucketed find-or-put table: storage management, the batch find-or-put
+// kernel and the random-access bandwidth probe (Sec. 4.1, 4.2 and the isolated
+// insert experiment of Sec. 5.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gx_internal.hpp"
+
+namespace gx {
+
+// ------------------------------------------------------------------ kernels
+__global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint64_t* counters) {
+  const uint4 e = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+       i += stride) {
+    p[i] = e;
+  }
+  if (counters && blockIdx.x == 0 && threadIdx.x < kNumCounters) counters[threadIdx.x] = 0;
+}
+
+template <int S>
+__device__ inline void load_key(const uint32_t* keys, uint32_t w, uint64_t idx,
+                                uint32_t (&k)[S]) {
+  if constexpr (S == 1) {
+    k[0] = keys[idx];
+  } else if constexpr (S == 2) {
+    uint2 t = reinterpret_cast<const uint2*>(keys)[idx];
+    k[0] = t.x;
+    k[1] = t.y;
+  } else {
+    if (w == 4) {
+      uint4 t = reinterpret_cast<const uint4*>(keys)[idx];
+      k[0] = t.x;
+      k[1] = t.y;
+      k[2] = t.z;
+      k[3] = t.w;
+    } else {
+      const uint32_t* p = keys + idx * 3;
+      k[0] = p[0];
+      k[1] = p[1];
+      k[2] = p[2];
+      k[3] = 0;
+    }
+  }
+}
+
+// One wavefront handles SUBS*U consecutive keys per round: subgroup sg takes
+// keys base + u*SUBS + sg, so the key reads and status writes of a round are
+// contiguous.  Grid-stride over rounds.
+template <int S, int B, int G, int U>
+__global__ __launch_bounds__(256) void fop_kernel(TableDev t, const uint32_t* keys, uint32_t w,
+                                                  uint64_t n, uint8_t* status, uint64_t* n_new) {
+  using Gm = Geo<S, B, G>;
+  const int lane = __lane_id();
+  const int sg = lane / G;
+  const int li = lane % G;
+  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+  constexpr uint64_t per_round = static_cast<uint64_t>(Gm::SUBS) * U;
+  LaneStats st;
+  for (uint64_t base = wave * per_round; base < n; base += n_waves * per_round) {
+    uint32_t key[U][S];
+    bool act[U];
+    uint8_t res[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t idx = base + static_cast<uint64_t>(u) * Gm::SUBS + sg;
+      act[u] = idx < n;
+#pragma unroll
+      for (int x = 0; x < S; ++x) key[u][x] = 0;
+      if (act[u]) load_key<S>(keys, w, idx, key[u]);
+    }
+    find_or_put<S, B, G, U>(t, key, act, res, st);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t idx = base + static_cast<uint64_t>(u) * Gm::SUBS + sg;
+      if (act[u] && li == 0) status[idx] = res[u];
+    }
+  }
+  flush_stats(t, st, n_new);
+}
+
+// Random-access probe: subgroups of LANES lanes read LANES*4 contiguous bytes
+// at a pseudo-random granule, 4 reads in flight per subgroup.
+template <int LANES>
+__global__ __launch_bounds__(256) void gather_probe_kernel(const uint32_t* buf, uint64_t n_gran,
+                                                           uint64_t n_reads, uint64_t seed,
+                                                           uint64_t* sink) {
+  constexpr int SUBS = 64 / LANES;
+  constexpr int R = 4;
+  const int lane = __lane_id();
+  const int sg = lane / LANES;
+  const int li = lane % LANES;
+  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+  constexpr uint64_t per_round = static_cast<uint64_t>(SUBS) * R;
+  uint32_t acc = 0;
+  for (uint64_t base = wave * per_round; base < n_reads; base += n_waves * per_round) {
+    uint32_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t idx = base + static_cast<uint64_t>(r) * SUBS + sg;
+      v[r] = 0;
+      if (idx < n_reads) {
+        const uint64_t g = mulhi64(fmix64(seed ^ (idx * kGolden)), n_gran);
+        v[r] = buf[g * LANES + li];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc += v[r];
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(sink), acc);
+}
+
+// ------------------------------------------------------------------ dispatch
+uint32_t resident_grid(int device, uint32_t per_cu) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return static_cast<uint32_t>(cus) * per_cu;
+}
+
+namespace {
+
+struct FopArgs {
+  TableDev t;
+  const uint32_t* keys;
+  uint32_t w;
+  uint64_t n;
+  uint8_t* status;
+  uint64_t* n_new;
+  uint32_t grid;
+  hipStream_t stream;
+};
+
+template <int S, int B, int G, int U>
+hipError_t launch_fop(const FopArgs& a) {
+  constexpr uint64_t per_block = static_cast<uint64_t>(4) * (64 / G) * U;  // 4 waves
+  uint64_t want = (a.n + per_block - 1) / per_block;
+  uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(want, a.grid));
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL((fop_kernel<S, B, G, U>), dim3(grid), dim3(256), 0, a.stream, a.t, a.keys,
+                     a.w, a.n, a.status, a.n_new);
+  return hipGetLastError();
+}
+
+template <int S, int B, int G>
+hipError_t dispatch_u(uint32_t U, const FopArgs& a) {
+  switch (U) {
+    case 1: return launch_fop<S, B, G, 1>(a);
+    case 2: return launch_fop<S, B, G, 2>(a);
+    case 4: return launch_fop<S, B, G, 4>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int S, int B>
+hipError_t dispatch_g(uint32_t G, uint32_t U, const FopArgs& a) {
+  switch (G) {
+    case 8: return dispatch_u<S, B, 8>(U, a);
+    case 16: return dispatch_u<S, B, 16>(U, a);
+    case 32: return dispatch_u<S, B, 32>(U, a);
+    case 64: return dispatch_u<S, B, 64>(U, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int S>
+hipError_t dispatch_b(uint32_t B, uint32_t G, uint32_t U, const FopArgs& a) {
+  switch (B) {
+    case 8: return dispatch_g<S, 8>(G, U, a);
+    case 16: return dispatch_g<S, 16>(G, U, a);
+    case 32: return dispatch_g<S, 32>(G, U, a);
+    case 64: return dispatch_g<S, 64>(G, U, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t n,
+                              uint8_t* status, uint64_t* n_new, hipStream_t stream) {
+  FopArgs a{t->dev(), keys, t->w, n, status, n_new, resident_grid(t->device, 8), stream};
+  switch (t->S) {
+    case 1: return dispatch_b<1>(t->B, t->G, t->U, a);
+    case 2: return dispatch_b<2>(t->B, t->G, t->U, a);
+    case 4: return dispatch_b<4>(t->B, t->G, t->U, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+namespace {
+
+hipError_t clear_storage(const gx_table* t, hipStream_t stream) {
+  const uint64_t n16 = t->n_buckets * t->B / 4;
+  const uint64_t want = (n16 + 255) / 256;
+  const uint32_t grid =
+      static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(want, resident_grid(t->device, 8))));
+  hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream,
+                     reinterpret_cast<uint4*>(t->words), n16, t->counters);
+  return hipGetLastError();
+}
+
+bool pow2_in(uint32_t x, uint32_t lo, uint32_t hi) {
+  return x >= lo && x <= hi && (x & (x - 1)) == 0;
+}
+
+void free_table(gx_table* t) {
+  if (!t) return;
+  if (t->words) (void)hipFree(t->words);
+  if (t->hc) (void)hipFree(t->hc);
+  if (t->counters) (void)hipFree(t->counters);
+  delete t;
+}
+
+}  // namespace
+}  // namespace gx
+
+// ====================================================================== ABI
+using gx::kEmpty;
+
+extern "C" {
+
+const char* gx_status_str(gx_status s) {
+  switch (s) {
+    case GX_OK: return "GX_OK";
+    case GX_EINVAL: return "GX_EINVAL: invalid argument";
+    case GX_ENOMEM: return "GX_ENOMEM: out of memory or buffer too small";
+    case GX_ETABLEFULL: return "GX_ETABLEFULL: hash functions exhausted";
+    case GX_EDEVICE: return "GX_EDEVICE: HIP runtime error";
+    case GX_EBUSY: return "GX_EBUSY";
+    case GX_ECANCELED: return "GX_ECANCELED";
+  }
+  return "unknown gx_status";
+}
+
+gx_status gx_table_create(uint32_t w, uint32_t B, uint64_t capacity, const gx_table_opts* opts,
+                          gx_table** out) {
+  if (!out || w < 1 || w > 4 || !gx::pow2_in(B, 8, 64) || capacity == 0) return GX_EINVAL;
+  const uint32_t S = gx::slot_words(w);
+  uint32_t G = opts && opts->subgroup ? opts->subgroup : std::min<uint32_t>(B, 64);
+  uint32_t U = opts && opts->keys_per_subgroup ? opts->keys_per_subgroup : 1;
+  uint32_t H = opts && opts->max_hashes ? opts->max_hashes : 8;
+  uint64_t seed = opts && opts->hash_seed ? opts->hash_seed : 0x1801058570ull;
+  if (!gx::pow2_in(G, 8, 64) || !(U == 1 || U == 2 || U == 4) || H > 4096) return GX_EINVAL;
+  const uint64_t slots_per_bucket = B / S;
+  const uint64_t n_buckets = (capacity + slots_per_bucket - 1) / slots_per_bucket;
+  if (n_buckets > (uint64_t(1) << 40)) return GX_EINVAL;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GX_EDEVICE;
+  gx_table* t = new (std::nothrow) gx_table;
+  if (!t) return GX_ENOMEM;
+  t->device = dev;
+  t->w = w;
+  t->S = S;
+  t->B = B;
+  t->G = G;
+  t->U = U;
+  t->H = H;
+  t->seed = seed;
+  t->n_buckets = n_buckets;
+  std::vector<uint64_t> hc(2 * H);
+  for (uint32_t j = 0; j < H; ++j) gx::hash_constants(seed, j, &hc[2 * j], &hc[2 * j + 1]);
+  t->a0 = hc[0];
+  t->c0 = hc[1];
+  if (hipMalloc(&t->words, n_buckets * B * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&t->hc, hc.size() * sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc(&t->counters, gx::kNumCounters * sizeof(uint64_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    gx::free_table(t);
+    return GX_ENOMEM;
+  }
+  if (hipMemcpy(t->hc, hc.data(), hc.size() * sizeof(uint64_t), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      gx::clear_storage(t, nullptr) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+    gx::free_table(t);
+    return GX_EDEVICE;
+  }
+  *out = t;
+  return GX_OK;
+}
+
+gx_status gx_table_destroy(gx_table* t) {
+  if (!t) return GX_OK;
+  (void)hipDeviceSynchronize();
+  gx::free_table(t);
+  return GX_OK;
+}
+
+gx_status gx_table_clear(gx_table* t, void* stream) {
+  if (!t) return GX_EINVAL;
+  return gx::clear_storage(t, static_cast<hipStream_t>(stream)) == hipSuccess ? GX_OK
+                                                                              : GX_EDEVICE;
+}
+
+gx_status gx_find_or_put(gx_table* t, const uint32_t* keys, uint64_t n, uint8_t* status,
+                         uint64_t* n_new, void* stream) {
+  if (!t) return GX_EINVAL;
+  if (n == 0) return GX_OK;
+  if (!keys || !status) return GX_EINVAL;
+  const uintptr_t align = t->S == 1 ? 4 : (t->S == 2 ? 8 : (t->w == 4 ? 16 : 4));
+  if (reinterpret_cast<uintptr_t>(keys) % align != 0) return GX_EINVAL;
+  if (n_new && reinterpret_cast<uintptr_t>(n_new) % 8 != 0) return GX_EINVAL;
+  return gx::launch_find_or_put(t, keys, n, status, n_new, static_cast<hipStream_t>(stream)) ==
+                 hipSuccess
+             ? GX_OK
+             : GX_EDEVICE;
+}
+
+gx_status gx_table_get_info(const gx_table* t, gx_table_info* out) {
+  if (!t || !out) return GX_EINVAL;
+  out->words_per_state = t->w;
+  out->slot_words = t->S;
+  out->bucket_words = t->B;
+  out->subgroup = t->G;
+  out->keys_per_subgroup = t->U;
+  out->max_hashes = t->H;
+  out->n_buckets = t->n_buckets;
+  out->n_slots = t->n_buckets * (t->B / t->S);
+  out->hash_seed = t->seed;
+  out->bytes = t->n_buckets * t->B * sizeof(uint32_t);
+  return GX_OK;
+}
+
+gx_status gx_table_stats(gx_table* t, gx_stats* out) {
+  if (!t || !out) return GX_EINVAL;
+  uint64_t c[gx::kNumCounters];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(c, t->counters, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
+    return GX_EDEVICE;
+  out->stored = c[gx::kCntStored];
+  out->lookups = c[gx::kCntLookups];
+  out->probes = c[gx::kCntProbes];
+  out->full = c[gx::kCntFull];
+  out->invalid = c[gx::kCntInvalid];
+  out->max_hash_index = static_cast<uint32_t>(c[gx::kCntMaxJ]);
+  out->reserved = 0;
+  return GX_OK;
+}
+
+gx_status gx_table_read_raw(gx_table* t, uint32_t* host, uint64_t first, uint64_t n_words) {
+  if (!t || (!host && n_words)) return GX_EINVAL;
+  const uint64_t total = t->n_buckets * t->B;
+  if (first > total || n_words > total - first) return GX_EINVAL;
+  if (n_words == 0) return GX_OK;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(host, t->words + first, n_words * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return GX_EDEVICE;
+  return GX_OK;
+}
+
+gx_status gx_table_dump(gx_table* t, uint32_t* host_keys, uint64_t cap, uint64_t* n_out) {
+  if (!t || !n_out) return GX_EINVAL;
+  const uint64_t total = t->n_buckets * t->B;
+  std::vector<uint32_t> raw;
+  try {
+    raw.resize(total);
+  } catch (...) {
+    return GX_ENOMEM;
+  }
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(raw.data(), t->words, total * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return GX_EDEVICE;
+  const uint32_t S = t->S, w = t->w;
+  const uint64_t n_slots = total / S;
+  uint64_t count = 0;
+  for (uint64_t s = 0; s < n_slots; ++s) count += raw[s * S] != kEmpty ? 1 : 0;
+  *n_out = count;
+  if (!host_keys || cap < count) return GX_ENOMEM;
+  if (w <= 2) {
+    std::vector<uint64_t> v;
+    v.reserve(count);
+    for (uint64_t s = 0; s < n_slots; ++s) {
+      if (raw[s * S] == kEmpty) continue;
+      uint64_t x = w == 1 ? raw[s] : (static_cast<uint64_t>(raw[s * 2]) << 32) | raw[s * 2 + 1];
+      v.push_back(x);  // word0 in the high half: numeric order is lexicographic
+    }
+    std::sort(v.begin(), v.end());
+    for (uint64_t i = 0; i < count; ++i) {
+      if (w == 1) {
+        host_keys[i] = static_cast<uint32_t>(v[i]);
+      } else {
+        host_keys[2 * i] = static_cast<uint32_t>(v[i] >> 32);
+        host_keys[2 * i + 1] = static_cast<uint32_t>(v[i]);
+      }
+    }
+  } else {
+    std::vector<std::array<uint32_t, 4>> v;
+    v.reserve(count);
+    for (uint64_t s = 0; s < n_slots; ++s) {
+      if (raw[s * 4] == kEmpty) continue;
+      v.push_back({raw[s * 4], raw[s * 4 + 1], raw[s * 4 + 2], w == 4 ? raw[s * 4 + 3] : 0u});
+    }
+    std::sort(v.begin(), v.end());
+    for (uint64_t i = 0; i < count; ++i)
+      for (uint32_t k = 0; k < w; ++k) host_keys[i * w + k] = v[i][k];
+  }
+  return GX_OK;
+}
+
+gx_status gx_hash_bucket(const uint32_t* key, uint32_t w, uint64_t seed, uint32_t j,
+                         uint64_t n_buckets, uint64_t* bucket) {
+  if (!key || !bucket || w < 1 || w > 4 || n_buckets == 0) return GX_EINVAL;
+  if (seed == 0) seed = 0x1801058570ull;
+  uint64_t a, c, mix;
+  gx::hash_constants(seed, j, &a, &c);
+  if (w == 1) {
+    const uint32_t k[1] = {key[0]};
+    mix = gx::key_mix<1>(k, seed);
+  } else if (w == 2) {
+    const uint32_t k[2] = {key[0], key[1]};
+    mix = gx::key_mix<2>(k, seed);
+  } else {
+    const uint32_t k[4] = {key[0], key[1], key[2], w == 4 ? key[3] : 0u};
+    mix = gx::key_mix<4>(k, seed);
+  }
+  *bucket = gx::bucket_of(mix, a, c, n_buckets);
+  return GX_OK;
+}
+
+gx_status gx_gather_probe(const uint32_t* buf, uint64_t buf_bytes, uint32_t granule,
+                          uint64_t n_reads, uint64_t seed, uint64_t* sink, void* stream) {
+  if (!buf || !sink || !gx::pow2_in(granule, 4, 256) || buf_bytes < granule) return GX_EINVAL;
+  if (reinterpret_cast<uintptr_t>(buf) % granule != 0) return GX_EINVAL;
+  if (n_reads == 0) return GX_OK;
+  const uint64_t n_gran = buf_bytes / granule;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GX_EDEVICE;
+  const uint32_t lanes = granule / 4;
+  const uint64_t per_block = 4ull * (64 / lanes) * 4;
+  const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(
+      1, std::min<uint64_t>((n_reads + per_block - 1) / per_block, gx::resident_grid(dev, 8))));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (lanes) {
+#define GX_PROBE_CASE(L)                                                                     \
+  case L:                                                                                    \
+    hipLaunchKernelGGL(gx::gather_probe_kernel<L>, dim3(grid), dim3(256), 0, st, buf, n_gran, \
+                       n_reads, seed, sink);                                                 \
+    break;
+    GX_PROBE_CASE(1)
+    GX_PROBE_CASE(2)
+    GX_PROBE_CASE(4)
+    GX_PROBE_CASE(8)
+    GX_PROBE_CASE(16)
+    GX_PROBE_CASE(32)
+    GX_PROBE_CASE(64)
+#undef GX_PROBE_CASE
+    default:
+      return GX_EINVAL;
+  }
+  return hipGetLastError() == hipSuccess ? GX_OK : GX_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+"""GPU parity of gx_explore against the oracle BFS: reachable-state count,
+per-level counts, transition count, deadlock set and the final table contents,
+all bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1801_05857_amd as gx
+import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gx.lib()
+    return torch.device("cuda:0")
+
+
+def _explore_and_compare(net, B=32, G=0, cap=None, check_dump=True, **kw):
+    want = oracle.explore(net, want_visited=check_dump)
+    w = want.words
+    cap = cap or max(64, 2 * want.n_states)
+    # buckets of 2 or 4 slots at load 0.5 can exhaust 8 hash functions
+    kw.setdefault("max_hashes", 64)
+    with gx.Table(w, B, cap, subgroup=G, **kw) as t:
+        got = gx.explore(net, t)
+        assert got.words_per_state == w
+        assert got.n_states == want.n_states
+        assert got.levels.tolist() == want.levels.tolist()
+        assert got.n_transitions == want.n_transitions
+        assert np.array_equal(got.deadlocks, want.deadlocks)
+        if check_dump:
+            assert np.array_equal(t.dump(), want.visited)
+        s = t.stats()
+        assert s.stored == want.n_states and s.full == 0
+    return got
+
+
+def test_fig1(dev):
+    got = _explore_and_compare(W.fig1_producer_consumers())
+    assert (got.n_states, got.n_transitions) == (8, 24)
+
+
+def test_tiny_cycles_config(dev):
+    # the tiny configuration: one-word states, table of 2^16 words, buckets of 32
+    got = _explore_and_compare(W.tiny_cycles(), B=32, cap=(1 << 16))
+    assert got.n_states == 4096 and len(got.levels) == 21
+
+
+@pytest.mark.parametrize("n", list(range(2, 13)))
+def test_token_ring(dev, n):
+    got = _explore_and_compare(W.token_ring(n), B=32)
+    assert got.n_states == 2 * n * 3 ** (n - 1)
+
+
+@pytest.mark.parametrize("sizes", [(8, 8, 8, 8), (3, 5, 7, 11, 13), (2,) * 20, (64, 64, 64)])
+def test_independent_cycles(dev, sizes):
+    _explore_and_compare(W.independent_cycles(sizes), B=16)
+
+
+SPECS = [(B, G) for B in (8, 16, 32, 64) for G in (8, 16, 32, 64)]
+
+
+def _net_for_words(w):
+    # 1 word: 6 processes of 16 states; 2: 8 x 32; 3: 12 x 64; 4: 16 x 64
+    if w == 1:
+        return W.random_lts(101, 6, 16, 6, 3, 32, 0.25, 0.1)
+    if w == 2:
+        return W.random_lts(202, 8, 32, 4, 3, 32, 0.25, 0.1)
+    if w == 3:
+        return W.random_lts(303, 12, 64, 3, 3, 32, 0.25, 0.1)
+    return W.random_lts(404, 16, 64, 2, 3, 32, 0.25, 0.0)
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 4])
+@pytest.mark.parametrize("B,G", SPECS, ids=[f"B{B}-G{G}" for B, G in SPECS])
+def test_random_networks_every_specialisation(dev, w, B, G):
+    net = _net_for_words(w)
+    got = _explore_and_compare(net, B=B, G=G)
+    assert got.words_per_state == w
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_networks_with_deadlocks(dev, seed):
+    net = W.random_lts(seed, 5 + seed % 4, 16, 5, 2, 16, 0.3, 0.3)
+    _explore_and_compare(net, B=16, G=16)
+
+
+def test_larger_random_network(dev):
+    # about 10^6 states; chunked staging (tiles with many successors)
+    net = W.random_lts(7, 9, 64, 5, 4, 32, 0.25, 0.05)
+    got = _explore_and_compare(net, B=32, G=32, check_dump=False)
+    assert got.n_states > 100_000
+
+
+def test_table_full_is_reported(dev):
+    net = W.token_ring(8)  # 34992 states
+    with gx.Table(1, 8, 4096, max_hashes=2) as t:
+        with pytest.raises(gx.GxError) as e:
+            gx.explore(net, t)
+        assert e.value.code == gx.GX_ETABLEFULL
+        # invariants still hold: what is stored is reachable and unique
+        dump = t.dump()
+        want = oracle.explore(net, want_visited=True).visited
+        assert np.unique(dump, axis=0).shape[0] == dump.shape[0]
+        assert np.isin(dump.view(np.uint32).ravel(), want.ravel()).all()
+
+
+def test_frontier_overflow_is_reported(dev):
+    net = W.token_ring(9)
+    with gx.Table(1, 32, 1 << 18) as t:
+        with pytest.raises(gx.GxError) as e:
+            gx.explore(net, t, frontier_capacity=64)
+        assert e.value.code == gx.GX_ENOMEM
+
+
+def test_non_empty_table_rejected(dev):
+    net = W.token_ring(4)
+    with gx.Table(1, 32, 1024) as t:
+        gx.explore(net, t)
+        with pytest.raises(gx.GxError) as e:
+            gx.explore(net, t)
+        assert e.value.code == gx.GX_EINVAL
+        t.clear()
+        got = gx.explore(net, t)
+        assert got.n_states == 216
+
+
+def test_word_count_mismatch_rejected(dev):
+    with gx.Table(2, 32, 1024) as t:
+        with pytest.raises(gx.GxError) as e:
+            gx.explore(W.token_ring(4), t)
+        assert e.value.code == gx.GX_EINVAL

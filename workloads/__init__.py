@@ -268,3 +268,55 @@ def duplicated_stream(n_distinct: int, dup: int, w: int, seed: int) -> np.ndarra
     n = n_distinct * dup
     order = permutation(n, seed ^ 0x5EED5EED5EED5EED)
     return keys[(order % np.uint64(n_distinct)).astype(np.int64)]
+
+
+# ------------------------------------------- the same key streams, on device
+def _mix62_torch(x):
+    """``_mix62`` on an int64 torch tensor of values in [0, 2^62) (the
+    products wrap modulo 2^64 and are masked back to 62 bits)."""
+    import torch
+
+    m = (1 << 62) - 1
+
+    def i64(c):
+        return c - (1 << 64) if c >= (1 << 63) else c
+
+    x = x & m
+    x = (x * i64(0x9FB21C651E98DF25)) & m
+    x = x ^ (x >> 29)
+    x = (x * i64(0xD6E8FEB86659FD93)) & m
+    x = x ^ (x >> 32)
+    x = (x * i64(0x94D049BB133111EB)) & m
+    x = x ^ (x >> 29)
+    return x
+
+
+def duplicated_stream_torch(n_distinct: int, dup: int, seed: int, device):
+    """``duplicated_stream(n_distinct, dup, 2, seed)`` generated with torch on
+    ``device`` (two-word keys, n_distinct * dup a power of two).  Returns the
+    (n, 2) int32 key tensor and the int64 tensor of distinct-key indices per
+    position."""
+    import torch
+
+    n = n_distinct * dup
+    if n & (n - 1):
+        raise ValueError("n_distinct * dup must be a power of two")
+    bits = max(1, (n - 1).bit_length())
+    mask = (1 << bits) - 1
+    rng = SplitMix64(seed ^ 0x5EED5EED5EED5EED)
+
+    def i64(c):
+        return c - (1 << 64) if c >= (1 << 63) else c
+
+    y = torch.arange(n, dtype=torch.int64, device=device)
+    for _ in range(3):
+        a, b = rng.next() | 1, rng.next()
+        y = (y * i64(a) + i64(b)) & mask
+        y = y ^ (y >> max(1, bits // 2))
+    idx = y % n_distinct
+    c = (idx + (seed & MASK62)) & MASK62
+    x = _mix62_torch(c)
+    keys = torch.empty((n, 2), dtype=torch.int32, device=device)
+    keys[:, 0] = (x & 0x7FFFFFFF).to(torch.int32)
+    keys[:, 1] = (x >> 31).to(torch.int32)
+    return keys, idx
