@@ -57,7 +57,7 @@ typedef struct {
   uint32_t max_hashes; /* H, hash functions tried before a key is FULL; 0 -> 8      */
   uint32_t subgroup;   /* lanes that probe one bucket: 8, 16, 32 or 64; 0 -> the
                           smaller of bucket_words and 64                         */
-  uint32_t keys_per_subgroup; /* keys a subgroup keeps in flight: 1, 2 or 4;
+  uint32_t keys_per_subgroup; /* keys a subgroup keeps in flight: 1, 2, 4 or 8;
                                  0 -> 1                                          */
   uint32_t reserved;
 } gx_table_opts;

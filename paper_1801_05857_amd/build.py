@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgx.so")
-SOURCES = ["gx_table.hip", "gx_explore.hip"]
+SOURCES = ["gx_table.hip", "gx_fop_s1.hip", "gx_fop_s2.hip", "gx_fop_s4.hip",
+           "gx_explore.hip", "gx_explore_s1.hip", "gx_explore_s2.hip", "gx_explore_s4.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -41,7 +42,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB):
         return LIB
     os.makedirs(OUT_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -291,12 +291,13 @@ __device__ inline void flush_stats(const TableDev& t, const LaneStats& st, uint6
   }
 }
 
-// Find-or-put of U keys per subgroup (every lane of a subgroup holds the same
-// keys).  act[u] false: no key.  On return res[u] holds kNew / kSeen / kFull /
-// kInvalid for active keys; hash index used in jres[u].  The call must be
-// reached by the whole wavefront (it ballots across it).
+// Find-or-put of U keys per subgroup.  Every lane of a subgroup holds the same
+// U keys (slot format, no word kEmpty), their 64-bit mixes and first buckets.
+// act[u] false: no key.  On return res[u] is kNew / kSeen / kFull for active
+// keys.  Must be reached by the whole wavefront (it ballots across it).
 template <int S, int B, int G, int U>
 __device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S],
+                                   const uint64_t (&mix)[U], const uint64_t (&bkt0)[U],
                                    const bool (&act_in)[U], uint8_t (&res)[U], LaneStats& st) {
   using Gm = Geo<S, B, G>;
   constexpr int K = Gm::K;
@@ -306,26 +307,16 @@ __device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S
 
   bool act[U];
   uint32_t j[U];
-  uint64_t mix[U];
   uint64_t bkt[U];
   uint32_t view[U][K];
 
+  // issue every first bucket read before looking at any of them
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     act[u] = act_in[u];
     res[u] = kSeen;
     j[u] = 0;
-    bool bad = false;
-#pragma unroll
-    for (int w = 0; w < S; ++w) bad |= key[u][w] == kEmpty;
-    if (act[u] && bad) {
-      res[u] = kInvalid;
-      act[u] = false;
-      if (li == 0) ++st.invalid;
-    }
-    if (act[u] && li == 0) ++st.lookups;
-    mix[u] = key_mix<S>(key[u], t.seed);
-    bkt[u] = bucket_of(mix[u], t.a0, t.c0, t.n_buckets);
+    bkt[u] = bkt0[u];
 #pragma unroll
     for (int w = 0; w < K; ++w) view[u][w] = kEmpty;
     if (act[u]) {
@@ -339,89 +330,45 @@ __device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S
 #pragma unroll
     for (int u = 0; u < U; ++u) any |= act[u];
     if (!__any(any)) break;
+    // Pass 1: compare every view; issue the compare-and-swaps and next-bucket
+    // reads of all U keys before consuming any result, so the U round trips
+    // of a subgroup overlap.
+    bool claiming[U], reread[U];
+    int cl[U], cw[U];
+    uint64_t old[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      claiming[u] = false;
+      reread[u] = false;
+      cl[u] = 0;
+      cw[u] = 0;
+      old[u] = ~0ull;
       if (!act[u]) continue;
       const Eval ev = evaluate<S, B, G>(view[u], key[u], li, shift);
-      uint32_t* const base = t.words + bkt[u] * B + li * K;
-      bool reread = false;
       if (ev.match) {
         res[u] = kSeen;
         act[u] = false;
       } else if (ev.partial) {
-        reread = true;
+        reread[u] = true;
       } else if (ev.claim_lane >= 0) {
-        bool won = false, same = false;
-        // the slot value the CAS observed (claiming lane only)
-        uint32_t o0 = kEmpty, o1 = kEmpty, o2 = kEmpty, o3 = kEmpty;
+        claiming[u] = true;
+        cl[u] = ev.claim_lane;
+        cw[u] = ev.claim_word;
         if (li == ev.claim_lane) {
-          uint32_t* slot = base + ev.claim_word;
+          uint32_t* slot = t.words + bkt[u] * B + li * K + ev.claim_word;
           if constexpr (S == 1) {
             uint32_t exp = kEmpty;
-            won = __hip_atomic_compare_exchange_strong(slot, &exp, key[u][0], __ATOMIC_RELAXED,
-                                                       __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            same = !won && exp == key[u][0];
-            o0 = exp;
+            __hip_atomic_compare_exchange_strong(slot, &exp, key[u][0], __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            old[u] = 0xFFFFFFFF00000000ull | exp;
           } else {
             const uint64_t head =
                 static_cast<uint64_t>(key[u][0]) | (static_cast<uint64_t>(key[u][1]) << 32);
             uint64_t exp = ~0ull;
-            won = __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t*>(slot), &exp,
-                                                       head, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            o0 = static_cast<uint32_t>(exp);
-            o1 = static_cast<uint32_t>(exp >> 32);
-            if constexpr (S == 2) {
-              same = !won && exp == head;
-            } else {
-              const uint64_t tail =
-                  static_cast<uint64_t>(key[u][2]) | (static_cast<uint64_t>(key[u][3]) << 32);
-              if (won) {
-                __hip_atomic_store(reinterpret_cast<uint64_t*>(slot + 2), tail, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-              } else if (exp == head) {
-                // same head: the tail decides (still kEmpty while its owner
-                // has not stored it, which leaves the slot PARTIAL)
-                const uint64_t got =
-                    __hip_atomic_load(reinterpret_cast<uint64_t*>(slot + 2), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-                same = got == tail;
-                o2 = static_cast<uint32_t>(got);
-                o3 = static_cast<uint32_t>(got >> 32);
-              } else {
-                // another key's head: the slot can never match, its tail is
-                // irrelevant (any non-kEmpty placeholder keeps it FINAL)
-                o2 = 0;
-                o3 = 0;
-              }
-            }
-          }
-        }
-        const uint64_t W = (__ballot(won) >> shift) & Gm::GMASK;
-        const uint64_t Sm = (__ballot(same) >> shift) & Gm::GMASK;
-        if (W) {
-          res[u] = kNew;
-          act[u] = false;
-          if (li == 0) ++st.stored;
-        } else if (Sm) {
-          res[u] = kSeen;
-          act[u] = false;
-        } else {
-          // Patch the view with what the CAS saw: that slot is no longer a
-          // candidate, so every failed CAS retires one slot for good and the
-          // loop makes progress whatever the plain loads returned.
-          const int src = shift + ev.claim_lane;
-          const uint32_t s0 = __shfl(o0, src, 64);
-          const uint32_t s1 = __shfl(o1, src, 64);
-          const uint32_t s2 = __shfl(o2, src, 64);
-          const uint32_t s3 = __shfl(o3, src, 64);
-          const int cw = ev.claim_lane * K + __shfl(ev.claim_word, src, 64);
-          const uint32_t sv[4] = {s0, s1, s2, s3};
-#pragma unroll
-          for (int x = 0; x < K; ++x) {
-            const int d = li * K + x - cw;
-            if (li < Gm::GE && d >= 0 && d < S) view[u][x] = key_word<4>(sv, d);
+            __hip_atomic_compare_exchange_strong(reinterpret_cast<uint64_t*>(slot), &exp, head,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            old[u] = exp;
           }
         }
       } else {
@@ -438,13 +385,136 @@ __device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S
           if (li == 0) ++st.probes;
         }
       }
-      if (reread) {
-        if (li < Gm::GE) load_view_fresh<K>(base, view[u]);
+    }
+    // Pass 2: consume the compare-and-swap results.  A CAS succeeded when it
+    // returned the empty slot value.
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!claiming[u]) continue;
+      bool won = false, same = false;
+      uint32_t o0 = kEmpty, o1 = kEmpty, o2 = kEmpty, o3 = kEmpty;
+      if (li == cl[u]) {
+        uint32_t* slot = t.words + bkt[u] * B + li * K + cw[u];
+        o0 = static_cast<uint32_t>(old[u]);
+        o1 = static_cast<uint32_t>(old[u] >> 32);
+        if constexpr (S == 1) {
+          won = o0 == kEmpty;
+          same = o0 == key[u][0];
+        } else {
+          const uint64_t head =
+              static_cast<uint64_t>(key[u][0]) | (static_cast<uint64_t>(key[u][1]) << 32);
+          won = old[u] == ~0ull;
+          if constexpr (S == 2) {
+            same = old[u] == head;
+          } else {
+            const uint64_t tail =
+                static_cast<uint64_t>(key[u][2]) | (static_cast<uint64_t>(key[u][3]) << 32);
+            if (won) {
+              // publish the tail in the same step as the claim is known
+              __hip_atomic_store(reinterpret_cast<uint64_t*>(slot + 2), tail, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+            } else if (old[u] == head) {
+              // same head: the tail decides (still kEmpty while its owner has
+              // not stored it, which leaves the slot PARTIAL)
+              const uint64_t got = __hip_atomic_load(reinterpret_cast<uint64_t*>(slot + 2),
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              same = got == tail;
+              o2 = static_cast<uint32_t>(got);
+              o3 = static_cast<uint32_t>(got >> 32);
+            } else {
+              // another key's head: the slot can never match; any non-kEmpty
+              // placeholder for its tail keeps it FINAL in the view
+              o2 = 0;
+              o3 = 0;
+            }
+          }
+        }
+      }
+      const uint64_t W = (__ballot(won) >> shift) & Gm::GMASK;
+      const uint64_t Sm = (__ballot(same) >> shift) & Gm::GMASK;
+      if (W) {
+        res[u] = kNew;
+        act[u] = false;
+        if (li == 0) ++st.stored;
+      } else if (Sm) {
+        res[u] = kSeen;
+        act[u] = false;
+      } else {
+        // Patch the view with what the CAS saw: that slot is no longer a
+        // candidate, so every failed CAS retires one slot for good and the
+        // loop makes progress whatever the plain loads returned.
+        const int src = shift + cl[u];
+        const uint32_t sv[4] = {__shfl(o0, src, 64), __shfl(o1, src, 64), __shfl(o2, src, 64),
+                                __shfl(o3, src, 64)};
+        const int c0 = cl[u] * K + __shfl(cw[u], src, 64);
+#pragma unroll
+        for (int x = 0; x < K; ++x) {
+          const int d = li * K + x - c0;
+          if (li < Gm::GE && d >= 0 && d < S) view[u][x] = key_word<4>(sv, d);
+        }
+      }
+    }
+    // Pass 3: re-read buckets that held a PARTIAL slot.
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (reread[u]) {
+        if (li < Gm::GE) load_view_fresh<K>(t.words + bkt[u] * B + li * K, view[u]);
         if (li == 0) ++st.probes;
       }
       if (!act[u] && li == 0 && res[u] != kFull && j[u] > st.max_j) st.max_j = j[u];
     }
   }
+}
+
+// Find-or-put of one key per lane: lane l of the wavefront owns key `own`
+// (slot format) when own_act.  Each lane hashes its own key (64 hashes per
+// wavefront, no redundant work); subgroup g then probes the keys owned by its
+// G lanes, U at a time, receiving key, mix and first bucket from the owner by
+// lane shuffles; the result comes back to the owner lane.  Returns the owner's
+// status (kNew / kSeen / kFull / kInvalid).  Must be reached by the whole
+// wavefront.
+template <int S, int B, int G, int U>
+__device__ inline uint8_t find_or_put_lanes(const TableDev& t, const uint32_t (&own)[S],
+                                            bool own_act, LaneStats& st) {
+  static_assert(U >= 1 && U <= G && (G % U) == 0, "keys in flight per subgroup");
+  const int lane = __lane_id();
+  const int li = lane % G;
+  const int first = lane - li;  // first lane of this subgroup
+  uint8_t own_res = kSeen;
+  bool bad = false;
+#pragma unroll
+  for (int w = 0; w < S; ++w) bad |= own[w] == kEmpty;
+  if (own_act && bad) {
+    own_res = kInvalid;
+    own_act = false;
+    ++st.invalid;
+  }
+  if (own_act) ++st.lookups;
+  const uint64_t own_mix = key_mix<S>(own, t.seed);
+  const uint64_t own_bkt = bucket_of(own_mix, t.a0, t.c0, t.n_buckets);
+#pragma unroll 1
+  for (int c = 0; c < G; c += U) {
+    uint32_t key[U][S];
+    uint64_t mix[U], bkt[U];
+    bool act[U];
+    uint8_t res[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int src = first + c + u;
+#pragma unroll
+      for (int w = 0; w < S; ++w) key[u][w] = __shfl(own[w], src, 64);
+      mix[u] = (static_cast<uint64_t>(__shfl(static_cast<uint32_t>(own_mix >> 32), src, 64)) << 32) |
+               __shfl(static_cast<uint32_t>(own_mix), src, 64);
+      bkt[u] = (static_cast<uint64_t>(__shfl(static_cast<uint32_t>(own_bkt >> 32), src, 64)) << 32) |
+               __shfl(static_cast<uint32_t>(own_bkt), src, 64);
+      act[u] = __shfl(static_cast<int>(own_act), src, 64) != 0;
+    }
+    find_or_put<S, B, G, U>(t, key, mix, bkt, act, res, st);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (li == c + u && own_act) own_res = res[u];
+  }
+  return own_res;
 }
 
 }  // namespace gx

@@ -41,6 +41,25 @@ namespace gx {
 
 inline uint32_t slot_words(uint32_t w) { return w == 3 ? 4u : w; }
 
+struct FopArgs {
+  TableDev t;
+  const uint32_t* keys;
+  uint32_t w;
+  uint64_t n;
+  uint8_t* status;
+  uint64_t* n_new;
+  uint32_t cus;  // compute units of the device
+  hipStream_t stream;
+};
+
+// Find-or-put dispatch over (B, G, U) for slot width S (one translation unit
+// per S).
+template <int S>
+hipError_t dispatch_b(uint32_t B, uint32_t G, uint32_t U, const FopArgs& a);
+extern template hipError_t dispatch_b<1>(uint32_t, uint32_t, uint32_t, const FopArgs&);
+extern template hipError_t dispatch_b<2>(uint32_t, uint32_t, uint32_t, const FopArgs&);
+extern template hipError_t dispatch_b<4>(uint32_t, uint32_t, uint32_t, const FopArgs&);
+
 // Launch the find-or-put kernel specialised for the table's (S, B, G, U).
 hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t n,
                               uint8_t* status, uint64_t* n_new, hipStream_t stream);

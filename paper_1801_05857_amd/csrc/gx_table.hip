@@ -25,68 +25,6 @@ __global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint6
   if (counters && blockIdx.x == 0 && threadIdx.x < kNumCounters) counters[threadIdx.x] = 0;
 }
 
-template <int S>
-__device__ inline void load_key(const uint32_t* keys, uint32_t w, uint64_t idx,
-                                uint32_t (&k)[S]) {
-  if constexpr (S == 1) {
-    k[0] = keys[idx];
-  } else if constexpr (S == 2) {
-    uint2 t = reinterpret_cast<const uint2*>(keys)[idx];
-    k[0] = t.x;
-    k[1] = t.y;
-  } else {
-    if (w == 4) {
-      uint4 t = reinterpret_cast<const uint4*>(keys)[idx];
-      k[0] = t.x;
-      k[1] = t.y;
-      k[2] = t.z;
-      k[3] = t.w;
-    } else {
-      const uint32_t* p = keys + idx * 3;
-      k[0] = p[0];
-      k[1] = p[1];
-      k[2] = p[2];
-      k[3] = 0;
-    }
-  }
-}
-
-// One wavefront handles SUBS*U consecutive keys per round: subgroup sg takes
-// keys base + u*SUBS + sg, so the key reads and status writes of a round are
-// contiguous.  Grid-stride over rounds.
-template <int S, int B, int G, int U>
-__global__ __launch_bounds__(256) void fop_kernel(TableDev t, const uint32_t* keys, uint32_t w,
-                                                  uint64_t n, uint8_t* status, uint64_t* n_new) {
-  using Gm = Geo<S, B, G>;
-  const int lane = __lane_id();
-  const int sg = lane / G;
-  const int li = lane % G;
-  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
-  constexpr uint64_t per_round = static_cast<uint64_t>(Gm::SUBS) * U;
-  LaneStats st;
-  for (uint64_t base = wave * per_round; base < n; base += n_waves * per_round) {
-    uint32_t key[U][S];
-    bool act[U];
-    uint8_t res[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t idx = base + static_cast<uint64_t>(u) * Gm::SUBS + sg;
-      act[u] = idx < n;
-#pragma unroll
-      for (int x = 0; x < S; ++x) key[u][x] = 0;
-      if (act[u]) load_key<S>(keys, w, idx, key[u]);
-    }
-    find_or_put<S, B, G, U>(t, key, act, res, st);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t idx = base + static_cast<uint64_t>(u) * Gm::SUBS + sg;
-      if (act[u] && li == 0) status[idx] = res[u];
-    }
-  }
-  flush_stats(t, st, n_new);
-}
-
 // Random-access probe: subgroups of LANES lanes read LANES*4 contiguous bytes
 // at a pseudo-random granule, 4 reads in flight per subgroup.
 template <int LANES>
@@ -129,67 +67,9 @@ uint32_t resident_grid(int device, uint32_t per_cu) {
   return static_cast<uint32_t>(cus) * per_cu;
 }
 
-namespace {
-
-struct FopArgs {
-  TableDev t;
-  const uint32_t* keys;
-  uint32_t w;
-  uint64_t n;
-  uint8_t* status;
-  uint64_t* n_new;
-  uint32_t grid;
-  hipStream_t stream;
-};
-
-template <int S, int B, int G, int U>
-hipError_t launch_fop(const FopArgs& a) {
-  constexpr uint64_t per_block = static_cast<uint64_t>(4) * (64 / G) * U;  // 4 waves
-  uint64_t want = (a.n + per_block - 1) / per_block;
-  uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(want, a.grid));
-  if (grid == 0) grid = 1;
-  hipLaunchKernelGGL((fop_kernel<S, B, G, U>), dim3(grid), dim3(256), 0, a.stream, a.t, a.keys,
-                     a.w, a.n, a.status, a.n_new);
-  return hipGetLastError();
-}
-
-template <int S, int B, int G>
-hipError_t dispatch_u(uint32_t U, const FopArgs& a) {
-  switch (U) {
-    case 1: return launch_fop<S, B, G, 1>(a);
-    case 2: return launch_fop<S, B, G, 2>(a);
-    case 4: return launch_fop<S, B, G, 4>(a);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int S, int B>
-hipError_t dispatch_g(uint32_t G, uint32_t U, const FopArgs& a) {
-  switch (G) {
-    case 8: return dispatch_u<S, B, 8>(U, a);
-    case 16: return dispatch_u<S, B, 16>(U, a);
-    case 32: return dispatch_u<S, B, 32>(U, a);
-    case 64: return dispatch_u<S, B, 64>(U, a);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int S>
-hipError_t dispatch_b(uint32_t B, uint32_t G, uint32_t U, const FopArgs& a) {
-  switch (B) {
-    case 8: return dispatch_g<S, 8>(G, U, a);
-    case 16: return dispatch_g<S, 16>(G, U, a);
-    case 32: return dispatch_g<S, 32>(G, U, a);
-    case 64: return dispatch_g<S, 64>(G, U, a);
-  }
-  return hipErrorInvalidValue;
-}
-
-}  // namespace
-
 hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t n,
                               uint8_t* status, uint64_t* n_new, hipStream_t stream) {
-  FopArgs a{t->dev(), keys, t->w, n, status, n_new, resident_grid(t->device, 8), stream};
+  FopArgs a{t->dev(), keys, t->w, n, status, n_new, resident_grid(t->device, 1), stream};
   switch (t->S) {
     case 1: return dispatch_b<1>(t->B, t->G, t->U, a);
     case 2: return dispatch_b<2>(t->B, t->G, t->U, a);
@@ -251,7 +131,7 @@ gx_status gx_table_create(uint32_t w, uint32_t B, uint64_t capacity, const gx_ta
   uint32_t U = opts && opts->keys_per_subgroup ? opts->keys_per_subgroup : 1;
   uint32_t H = opts && opts->max_hashes ? opts->max_hashes : 8;
   uint64_t seed = opts && opts->hash_seed ? opts->hash_seed : 0x1801058570ull;
-  if (!gx::pow2_in(G, 8, 64) || !(U == 1 || U == 2 || U == 4) || H > 4096) return GX_EINVAL;
+  if (!gx::pow2_in(G, 8, 64) || !gx::pow2_in(U, 1, 8) || H > 4096) return GX_EINVAL;
   const uint64_t slots_per_bucket = B / S;
   const uint64_t n_buckets = (capacity + slots_per_bucket - 1) / slots_per_bucket;
   if (n_buckets > (uint64_t(1) << 40)) return GX_EINVAL;

@@ -78,7 +78,7 @@ def _placement_ok(table, keys_sorted):
 
 
 GRID = [(w, B, G, U) for w in (1, 2, 3, 4) for B in (8, 16, 32, 64) for G in (8, 16, 32, 64)
-        for U in (1, 2, 4)]
+        for U in (1, 2, 4, 8)]
 
 
 @pytest.mark.parametrize("w,B,G,U", GRID, ids=[f"w{w}-B{B}-G{G}-U{U}" for w, B, G, U in GRID])
