@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--explore", action="store_true",
+                    help="explore random networks (see --net) instead of the find-or-put batch")
+    ap.add_argument("--net", action="append", default=[],
+                    help="seed:procs:nstates:live:degree:sinkprob (repeatable)")
+    ap.add_argument("--cap", type=float, default=1e9, help="table capacity in states (explore)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter scale reference)")
     return ap.parse_args()
@@ -180,6 +185,45 @@ def main():
             print(json.dumps({"probe_granule_bytes": g, "reads": n_reads, "ms": ms,
                               "Greads_per_s": n_reads / ms / 1e6,
                               "GB_per_s_useful": n_reads * g / ms / 1e6}), flush=True)
+        return
+
+    if args.explore:
+        for spec in args.net or ["1:12:64:5:3:0.2"]:
+            seed, P, ns, live, deg, sink = spec.split(":")
+            net = W.random_lts(int(seed), int(P), int(ns), int(live), int(deg), 32, 0.25,
+                               float(sink))
+            w = gx.network_words(net)
+            t = gx.Table(w, args.bucket, int(args.cap), subgroup=args.subgroup,
+                         keys_per_subgroup=args.kps, max_hashes=args.hashes or 64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                # first run: sizes the table-resident buffers; the timed run
+                # explores into the cleared table with every buffer resident
+                gx.explore(net, t)
+                cold = time.perf_counter() - t0
+                t.clear()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = gx.explore(net, t)
+                dt = time.perf_counter() - t0
+                s = t.stats()
+                per_state = (r.n_transitions / max(1, r.n_states))
+                S = t.info.slot_words
+                bps = per_state * max(4 * args.bucket, GRANULE) + 8 * S + GRANULE
+                print(json.dumps({"net": spec, "words": w, "states": r.n_states,
+                                  "transitions": r.n_transitions, "levels": len(r.levels),
+                                  "max_level": int(r.levels.max()), "deadlocks": len(r.deadlocks),
+                                  "seconds": round(dt, 4), "cold_seconds": round(cold, 4),
+                                  "states_per_s": round(r.n_states / dt),
+                                  "succ_per_state": round(per_state, 2),
+                                  "probes_per_lookup": round(s.probes / max(1, s.lookups), 4),
+                                  "algo_GBps": round(r.n_states * bps / dt / 1e9, 1),
+                                  "load": round(r.n_states / t.info.n_slots, 3)}), flush=True)
+            except gx.GxError as e:
+                print(json.dumps({"net": spec, "error": str(e),
+                                  "seconds": round(time.perf_counter() - t0, 3)}), flush=True)
+            t.close()
         return
 
     n = 1 << args.log2n

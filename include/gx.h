@@ -210,9 +210,10 @@ gx_status gx_network_pack(const gx_network* net, const uint32_t* local, uint64_t
                           uint32_t* out);
 
 typedef struct {
-  uint64_t frontier_capacity; /* states per BFS frontier buffer; 0 -> the table's
-                                 slot count                                    */
-  uint64_t deadlock_capacity; /* deadlock states kept; 0 -> 1<<20              */
+  uint64_t frontier_capacity; /* largest BFS level (states) the call may buffer;
+                                 0 -> limited by device memory only           */
+  uint64_t deadlock_capacity; /* largest deadlock count the call may buffer;
+                                 0 -> limited by device memory only           */
   void* hip_stream;           /* stream for every launch of the call           */
   uint32_t reserved[4];
 } gx_explore_opts;
@@ -237,6 +238,11 @@ typedef struct {
  *          gx_network_words(net); it holds the reachable set afterwards.
  *   opts   nullable.
  *   out    filled on success; free with gx_explore_result_free.
+ *
+ * Device buffers (frontiers, deadlock list, network image) are owned by the
+ * table, allocated on first use and grown on demand; later explorations into
+ * the same table reuse them.  A level is expanded in slices sized so that the
+ * next frontier cannot overflow even if every successor were new.
  *
  * Synchronous: returns when the exploration ends.
  * Errors: GX_EINVAL (invalid network, word count mismatch, non-empty table,

@@ -196,21 +196,33 @@ hipError_t launch_level_any(const gx_table* t, const ExploreArgs& a, uint32_t gr
   return hipErrorInvalidValue;
 }
 
-struct DeviceBuffers {
-  uint32_t* img = nullptr;
-  uint32_t* f[2] = {nullptr, nullptr};
-  uint32_t* dead = nullptr;
-  uint64_t* ctr = nullptr;
-  uint8_t* status = nullptr;
-  ~DeviceBuffers() {
-    if (img) (void)hipFree(img);
-    if (f[0]) (void)hipFree(f[0]);
-    if (f[1]) (void)hipFree(f[1]);
-    if (dead) (void)hipFree(dead);
-    if (ctr) (void)hipFree(ctr);
-    if (status) (void)hipFree(status);
+// Grow a device buffer of `cap` elements of `elem` bytes to at least `need`
+// elements, keeping its first `keep` elements.  Waits for the stream first.
+hipError_t grow(void** p, uint64_t* cap, uint64_t need, size_t elem, uint64_t keep,
+                hipStream_t stream) {
+  if (*cap >= need && *p) return hipSuccess;
+  uint64_t nc = std::max<uint64_t>(need, *cap + *cap / 2);
+  void* q = nullptr;
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&q, nc * elem);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
   }
-};
+  if (keep && *p) {
+    e = hipMemcpy(q, *p, keep * elem, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(q);
+      return e;
+    }
+  }
+  if (*p) (void)hipFree(*p);
+  *p = q;
+  *cap = nc;
+  return hipSuccess;
+}
+
 
 }  // namespace
 }  // namespace gx
@@ -258,41 +270,58 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   if (s != GX_OK) return s;
   if (ni.words != t->w) return GX_EINVAL;
   const uint32_t S = t->S;
-  const uint64_t n_slots = t->n_buckets * (t->B / S);
-  const uint64_t cap = opts && opts->frontier_capacity ? opts->frontier_capacity : n_slots;
-  const uint64_t dead_cap = opts && opts->deadlock_capacity ? opts->deadlock_capacity : (1u << 20);
+  const size_t state_bytes = S * sizeof(uint32_t);
+  // 0: limited only by device memory
+  const uint64_t max_cap = opts && opts->frontier_capacity ? opts->frontier_capacity : ~0ull;
+  const uint64_t max_dead = opts && opts->deadlock_capacity ? opts->deadlock_capacity : ~0ull;
   hipStream_t stream = opts ? static_cast<hipStream_t>(opts->hip_stream) : nullptr;
+  gx_explore_buffers& eb = t->eb;
+  const uint64_t max_succ = std::max<uint64_t>(1, ni.max_succ);
 
-  gx::DeviceBuffers d;
+  auto grow_buf = [&](uint32_t** p, uint64_t* cap, uint64_t need, uint64_t keep,
+                      uint64_t limit) -> gx_status {
+    if (*cap >= need && *p) return GX_OK;
+    if (need > limit) return GX_ENOMEM;
+    const uint64_t want = std::min<uint64_t>(limit, std::max<uint64_t>(need, 1u << 16));
+    const hipError_t e = gx::grow(reinterpret_cast<void**>(p), cap, want, state_bytes, keep,
+                                  stream);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GX_ENOMEM;
+    return e == hipSuccess ? GX_OK : GX_EDEVICE;
+  };
+
+  // resident buffers of the table (allocated on first use, grow-only)
   const uint32_t img_words = static_cast<uint32_t>(ni.img.size());
   const uint32_t img_stride = (img_words + 3) & ~3u;
-  if (hipMalloc(&d.img, img_stride * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&d.f[0], cap * S * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&d.f[1], cap * S * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&d.dead, dead_cap * S * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&d.ctr, 8 * sizeof(uint64_t)) != hipSuccess ||
-      hipMalloc(&d.status, 8) != hipSuccess) {
+  if (eb.img_cap < img_stride) {
+    if (gx::grow(reinterpret_cast<void**>(&eb.img), &eb.img_cap, img_stride, sizeof(uint32_t), 0,
+                 stream) != hipSuccess)
+      return GX_ENOMEM;
+  }
+  if (!eb.ctr && (hipMalloc(&eb.ctr, 8 * sizeof(uint64_t)) != hipSuccess ||
+                  hipMalloc(&eb.status, 8) != hipSuccess ||
+                  hipMalloc(&eb.key, 4 * sizeof(uint32_t)) != hipSuccess)) {
     (void)hipGetLastError();
     return GX_ENOMEM;
   }
+  for (int k = 0; k < 2; ++k)
+    if ((s = grow_buf(&eb.f[k], &eb.f_cap[k], 1, 0, max_cap)) != GX_OK) return s;
+  if ((s = grow_buf(&eb.dead, &eb.dead_cap, 1, 0, max_dead)) != GX_OK) return s;
+
   uint32_t init[4] = {0, 0, 0, 0};
   gx::pack_host(ni, ni.initial.data(), init);
   uint64_t ctr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (hipMemcpyAsync(d.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
+  if (hipMemcpyAsync(eb.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
                      stream) != hipSuccess ||
-      hipMemcpyAsync(d.f[0], init, S * sizeof(uint32_t), hipMemcpyHostToDevice, stream) !=
+      hipMemcpyAsync(eb.f[0], init, state_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(eb.key, init, t->w * sizeof(uint32_t), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
-      hipMemsetAsync(d.ctr, 0, 8 * sizeof(uint64_t), stream) != hipSuccess)
+      hipMemsetAsync(eb.ctr, 0, 8 * sizeof(uint64_t), stream) != hipSuccess)
     return GX_EDEVICE;
-  // the initial state: must be new, i.e. the table was empty of it
-  std::vector<uint32_t> init_key(init, init + t->w);
-  uint32_t* d_key = d.dead;  // borrow: the deadlock buffer is unused yet
-  if (hipMemcpyAsync(d_key, init_key.data(), t->w * sizeof(uint32_t), hipMemcpyHostToDevice,
-                     stream) != hipSuccess ||
-      gx::launch_find_or_put(t, d_key, 1, d.status, nullptr, stream) != hipSuccess)
+  // the initial state must be new, i.e. the table must not hold it yet
+  if (gx::launch_find_or_put(t, eb.key, 1, eb.status, nullptr, stream) != hipSuccess)
     return GX_EDEVICE;
   uint8_t st0 = 0;
-  if (hipMemcpyAsync(&st0, d.status, 1, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+  if (hipMemcpyAsync(&st0, eb.status, 1, hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return GX_EDEVICE;
   if (st0 == gx::kFull) return GX_ETABLEFULL;
@@ -300,40 +329,79 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
 
   gx::ExploreArgs a;
   a.t = t->dev();
-  a.img = d.img;
+  a.img = eb.img;
   a.img_words = img_words;
   a.img_stride = img_stride;
-  a.dead = d.dead;
-  a.dead_cap = dead_cap;
-  a.ctr = d.ctr;
-  a.cap_out = cap;
+  a.ctr = eb.ctr;
   const size_t lds = (img_stride + gx::kStageWords + 8) * sizeof(uint32_t);
-
-  std::vector<uint64_t> levels{1};
-  uint64_t n_in = 1;
-  int cur = 0;
-  while (n_in > 0) {
-    a.frontier_in = d.f[cur];
-    a.n_in = n_in;
-    a.frontier_out = d.f[cur ^ 1];
-    if (hipMemsetAsync(d.ctr, 0, sizeof(uint64_t), stream) != hipSuccess) return GX_EDEVICE;
-    const uint64_t grid = (n_in + 255) / 256;
-    if (grid > 0xFFFFFFFFull) return GX_ENOMEM;
-    if (gx::launch_level_any(t, a, static_cast<uint32_t>(grid), lds, stream) != hipSuccess)
-      return GX_EDEVICE;
-    if (hipMemcpyAsync(ctr, d.ctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+  auto read_ctr = [&]() -> gx_status {
+    if (hipMemcpyAsync(ctr, eb.ctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return GX_EDEVICE;
     if (ctr[3] & gx::kFlagTableFull) return GX_ETABLEFULL;
     if (ctr[3] & gx::kFlagFrontierOverflow) return GX_ENOMEM;
+    return GX_OK;
+  };
+
+  // Levels are expanded in slices small enough that even if every successor
+  // were new the next frontier (and the deadlock list) could not overflow:
+  // slice * max_succ <= free frontier room.  The exact fill is read back only
+  // when the room runs out; then the buffer grows (keeping its contents).
+  std::vector<uint64_t> levels{1};
+  uint64_t n_in = 1;
+  int cur = 0;
+  uint64_t dead_known = 0;
+  constexpr uint64_t kTargetSlice = 1u << 20;
+  while (n_in > 0) {
+    const int nxt = cur ^ 1;
+    if (hipMemsetAsync(eb.ctr, 0, sizeof(uint64_t), stream) != hipSuccess) return GX_EDEVICE;
+    uint64_t tail_known = 0, bound = 0, dead_bound = dead_known, pos = 0;
+    while (pos < n_in) {
+      uint64_t slice = std::min<uint64_t>(n_in - pos, (eb.f_cap[nxt] - bound) / max_succ);
+      slice = std::min<uint64_t>(slice, eb.dead_cap - dead_bound);
+      if (slice == 0) {
+        if ((s = read_ctr()) != GX_OK) return s;
+        tail_known = bound = ctr[0];
+        dead_known = dead_bound = ctr[1];
+        const uint64_t want = std::min<uint64_t>(n_in - pos, kTargetSlice);
+        if (eb.f_cap[nxt] - bound < max_succ) {
+          s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], tail_known + want * max_succ, tail_known,
+                       max_cap);
+          if (s == GX_ENOMEM && tail_known + max_succ <= max_cap)
+            s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], max_cap, tail_known, max_cap);
+          if (s != GX_OK) return s;
+        }
+        if (eb.dead_cap - dead_bound < 1) {
+          s = grow_buf(&eb.dead, &eb.dead_cap, dead_known + want, dead_known, max_dead);
+          if (s == GX_ENOMEM && dead_known < max_dead)
+            s = grow_buf(&eb.dead, &eb.dead_cap, max_dead, dead_known, max_dead);
+          if (s != GX_OK) return s;
+        }
+        continue;
+      }
+      a.frontier_in = eb.f[cur] + pos * S;
+      a.n_in = slice;
+      a.frontier_out = eb.f[nxt];
+      a.cap_out = eb.f_cap[nxt];
+      a.dead = eb.dead;
+      a.dead_cap = eb.dead_cap;
+      const uint64_t grid = (slice + 255) / 256;
+      if (gx::launch_level_any(t, a, static_cast<uint32_t>(grid), lds, stream) != hipSuccess)
+        return GX_EDEVICE;
+      pos += slice;
+      bound += slice * max_succ;
+      dead_bound += slice;
+    }
+    if ((s = read_ctr()) != GX_OK) return s;
+    dead_known = ctr[1];
     n_in = ctr[0];
     if (n_in) levels.push_back(n_in);
-    cur ^= 1;
+    cur = nxt;
   }
   const uint64_t n_dead = ctr[1];
-  if (n_dead > dead_cap) return GX_ENOMEM;
+  if (n_dead > eb.dead_cap) return GX_ENOMEM;
   std::vector<uint32_t> raw(n_dead * S);
-  if (n_dead && hipMemcpy(raw.data(), d.dead, raw.size() * sizeof(uint32_t),
+  if (n_dead && hipMemcpy(raw.data(), eb.dead, raw.size() * sizeof(uint32_t),
                           hipMemcpyDeviceToHost) != hipSuccess)
     return GX_EDEVICE;
   std::vector<std::array<uint32_t, 4>> dl(n_dead);

@@ -8,6 +8,20 @@
 #include "../../include/gx.h"
 #include "gx_device.hpp"
 
+// Device buffers of the exploration driver, owned by a table and reused by
+// every exploration into it (grow-only).
+struct gx_explore_buffers {
+  uint32_t* img = nullptr;  // network image
+  uint64_t img_cap = 0;     // words
+  uint32_t* f[2] = {nullptr, nullptr};
+  uint64_t f_cap[2] = {0, 0};  // states
+  uint32_t* dead = nullptr;
+  uint64_t dead_cap = 0;  // states
+  uint64_t* ctr = nullptr;  // 8 counters
+  uint8_t* status = nullptr;
+  uint32_t* key = nullptr;  // 4 words
+};
+
 struct gx_table {
   int device = 0;
   uint32_t w = 0;  // words per state
@@ -22,6 +36,7 @@ struct gx_table {
   uint64_t* hc = nullptr;        // 2*H hash constants
   uint64_t* counters = nullptr;  // gx::kNumCounters
   uint64_t a0 = 0, c0 = 0;
+  gx_explore_buffers eb;
 
   gx::TableDev dev() const {
     gx::TableDev t;
