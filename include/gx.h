@@ -259,6 +259,75 @@ void gx_explore_result_free(gx_explore_result* result);
 /* Static string naming a status code. */
 const char* gx_status_str(gx_status status);
 
+/* ------------------------------------------------------------ batches */
+
+/*
+ * Batched exploration: many networks (instances) explored by one persistent
+ * kernel launch per kernel class, each instance with its own table partition
+ * carved from one allocation.  Every instance follows exactly the
+ * single-exploration semantics of gx_explore (Sec. 3); instances advance
+ * level by level independently, workgroups pulling (instance, level, tile)
+ * work from a device-side queue.  Instances that share a kernel
+ * configuration (slot words, bucket words, subgroup, keys per subgroup) form a
+ * class; classes run concurrently on their own streams.
+ */
+typedef struct gx_batch gx_batch;
+
+typedef struct {
+  const uint64_t* capacity;   /* host, n entries, required: table capacity
+                                 (states) of each instance; also the size of
+                                 its two frontier buffers                     */
+  uint64_t hash_seed;         /* 0 -> the default seed                         */
+  uint32_t max_hashes;        /* H; 0 -> 8                                     */
+  uint32_t bucket_words;      /* 0 -> autotuned per instance, else 8|16|32|64 */
+  uint32_t subgroup;          /* 0 -> autotuned per instance, else 8|16        */
+  uint32_t keys_per_subgroup; /* 0 -> autotuned per instance, else 1|2         */
+  uint32_t use_graph;         /* nonzero: gx_batch_create captures a whole run
+                                 (clears, resets and every launch) in a hipGraph
+                                 and gx_batch_run replays it                   */
+  uint32_t max_levels;        /* BFS levels per instance; 0 -> 4096            */
+  uint64_t deadlock_capacity; /* deadlock records per class; 0 -> min(sum of
+                                 capacities, 2^26)                             */
+  void* hip_stream;           /* stream used by gx_explore_batch               */
+} gx_batch_opts;
+
+/* Compile every network (argument errors before device work), choose each
+ * instance's kernel configuration, allocate and upload.  Synchronous. */
+gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opts* opts,
+                          gx_batch** out);
+
+/* Clear every table and explore every instance from its initial state.
+ * Stream-ordered; may be called again to repeat the whole batch. */
+gx_status gx_batch_run(gx_batch* batch, void* hip_stream);
+
+/* Wait for the last run and fill outs[i] / inst_status[i] for every instance
+ * (GX_OK, GX_ETABLEFULL, GX_ENOMEM when a frontier, level or deadlock buffer
+ * was too small, GX_EDEVICE when the run was aborted).  outs of instances
+ * with GX_OK are freed with gx_explore_result_free.  Returns GX_EINVAL before
+ * any run. */
+gx_status gx_batch_results(gx_batch* batch, gx_explore_result* outs, gx_status* inst_status);
+
+/* Kernel configuration chosen for instance i (host only). */
+gx_status gx_batch_instance_config(const gx_batch* batch, uint32_t i, uint32_t* bucket_words,
+                                   uint32_t* subgroup, uint32_t* keys_per_subgroup);
+
+gx_status gx_batch_destroy(gx_batch* batch);
+
+/* create + run + results + destroy. */
+gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_opts* opts,
+                           gx_explore_result* outs, gx_status* inst_status);
+
+/*
+ * Autotuner: the (bucket words, subgroup, keys per subgroup) with the highest
+ * measured find-or-put rate on this device for keys of words_per_state words
+ * at the given final load factor (0 < load_factor <= 0.95).  The first call
+ * for a (slot words, load) pair times every candidate (B in 8..64, subgroup 8
+ * or 16, 1 or 2 keys per subgroup) on a synthetic stream of 2^21 keys; later
+ * calls return the cached choice.  Synchronous.
+ */
+gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bucket_words,
+                      uint32_t* subgroup, uint32_t* keys_per_subgroup);
+
 /* ------------------------------------------------------------ measurement */
 
 /*

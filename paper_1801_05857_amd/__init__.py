@@ -30,6 +30,8 @@ EXPORTED = [
     "gx_table_get_info", "gx_table_stats", "gx_table_dump", "gx_table_read_raw",
     "gx_hash_bucket", "gx_network_words", "gx_network_pack", "gx_explore",
     "gx_explore_result_free", "gx_status_str", "gx_gather_probe",
+    "gx_batch_create", "gx_batch_run", "gx_batch_results", "gx_batch_instance_config",
+    "gx_batch_destroy", "gx_explore_batch", "gx_autotune",
 ]
 
 
@@ -84,6 +86,14 @@ class _ExploreResult(ctypes.Structure):
                 ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32))]
 
 
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_void_p), ("hash_seed", ctypes.c_uint64),
+                ("max_hashes", ctypes.c_uint32), ("bucket_words", ctypes.c_uint32),
+                ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("max_levels", ctypes.c_uint32),
+                ("deadlock_capacity", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p)]
+
+
 _lib_handle = None
 
 
@@ -129,6 +139,22 @@ def lib() -> ctypes.CDLL:
         L.gx_status_str.argtypes = [st]
         L.gx_gather_probe.restype = st
         L.gx_gather_probe.argtypes = [vp, u64, u32, u64, u64, vp, vp]
+        L.gx_batch_create.restype = st
+        L.gx_batch_create.argtypes = [vp, u32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(vp)]
+        L.gx_batch_run.restype = st
+        L.gx_batch_run.argtypes = [vp, vp]
+        L.gx_batch_results.restype = st
+        L.gx_batch_results.argtypes = [vp, vp, vp]
+        L.gx_batch_instance_config.restype = st
+        L.gx_batch_instance_config.argtypes = [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                               ctypes.POINTER(u32)]
+        L.gx_batch_destroy.restype = st
+        L.gx_batch_destroy.argtypes = [vp]
+        L.gx_explore_batch.restype = st
+        L.gx_explore_batch.argtypes = [vp, u32, ctypes.POINTER(_BatchOpts), vp, vp]
+        L.gx_autotune.restype = st
+        L.gx_autotune.argtypes = [u32, ctypes.c_double, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                  ctypes.POINTER(u32)]
         _lib_handle = L
     return _lib_handle
 
@@ -321,6 +347,19 @@ class ExploreResult:
     deadlocks: np.ndarray
 
 
+def _take_result(res: _ExploreResult) -> ExploreResult:
+    w = res.words_per_state
+    levels = np.ctypeslib.as_array(res.level_counts, shape=(res.n_levels,)).copy()
+    if res.n_deadlocks:
+        dead = np.ctypeslib.as_array(res.deadlocks, shape=(res.n_deadlocks * w,)).copy()
+    else:
+        dead = np.zeros(0, np.uint32)
+    out = ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
+                        dead.reshape(-1, w))
+    lib().gx_explore_result_free(ctypes.byref(res))
+    return out
+
+
 def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity: int = 0,
             stream=None) -> ExploreResult:
     """gx_explore: BFS of the synchronous product into ``table``."""
@@ -329,17 +368,7 @@ def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity:
     res = _ExploreResult()
     _check(lib().gx_explore(ctypes.byref(h.c), table.handle, ctypes.byref(opts),
                             ctypes.byref(res)), "gx_explore")
-    try:
-        w = res.words_per_state
-        levels = np.ctypeslib.as_array(res.level_counts, shape=(res.n_levels,)).copy()
-        if res.n_deadlocks:
-            dead = np.ctypeslib.as_array(res.deadlocks, shape=(res.n_deadlocks * w,)).copy()
-        else:
-            dead = np.zeros(0, np.uint32)
-        return ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
-                             dead.reshape(-1, w))
-    finally:
-        lib().gx_explore_result_free(ctypes.byref(res))
+    return _take_result(res)
 
 
 def gather_probe(buf, granule: int, n_reads: int, seed: int, sink, stream=None) -> None:
@@ -347,3 +376,69 @@ def gather_probe(buf, granule: int, n_reads: int, seed: int, sink, stream=None) 
     _check(lib().gx_gather_probe(_dev_ptr(buf, "buf"), buf.numel() * buf.element_size(),
                                  granule, n_reads, seed, _dev_ptr(sink, "sink"),
                                  _stream_handle(stream)), "gx_gather_probe")
+
+
+# ------------------------------------------------------------------ batches
+def autotune(words_per_state: int, load_factor: float = 0.5) -> tuple[int, int, int]:
+    """gx_autotune: (bucket_words, subgroup, keys_per_subgroup) measured best."""
+    b, g, u = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().gx_autotune(words_per_state, load_factor, ctypes.byref(b), ctypes.byref(g),
+                             ctypes.byref(u)), "gx_autotune")
+    return int(b.value), int(g.value), int(u.value)
+
+
+class Batch:
+    """gx_batch: many explorations in one persistent launch per kernel class."""
+
+    def __init__(self, nets, capacity, *, hash_seed: int = 0, max_hashes: int = 0,
+                 bucket_words: int = 0, subgroup: int = 0, keys_per_subgroup: int = 0,
+                 use_graph: bool = False, max_levels: int = 0, deadlock_capacity: int = 0):
+        self.n = len(nets)
+        holders = [_NetHolder(net) for net in nets]
+        arr = (_Network * self.n)(*[h.c for h in holders])
+        cap = np.ascontiguousarray(capacity, dtype=np.uint64).reshape(-1)
+        if cap.shape[0] != self.n:
+            raise ValueError("one capacity per network")
+        opts = _BatchOpts(cap.ctypes.data, hash_seed, max_hashes, bucket_words, subgroup,
+                          keys_per_subgroup, int(use_graph), max_levels, deadlock_capacity, None)
+        h = ctypes.c_void_p()
+        _check(lib().gx_batch_create(arr, self.n, ctypes.byref(opts), ctypes.byref(h)),
+               "gx_batch_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().gx_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, stream=None) -> None:
+        _check(lib().gx_batch_run(self._h, _stream_handle(stream)), "gx_batch_run")
+
+    def results(self):
+        """List of (status, ExploreResult or None), one per instance."""
+        outs = (_ExploreResult * self.n)()
+        sts = (ctypes.c_int * self.n)()
+        _check(lib().gx_batch_results(self._h, outs, sts), "gx_batch_results")
+        return [(int(sts[i]), _take_result(outs[i]) if sts[i] == GX_OK else None)
+                for i in range(self.n)]
+
+    def instance_config(self, i: int) -> tuple[int, int, int]:
+        b, g, u = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().gx_batch_instance_config(self._h, i, ctypes.byref(b), ctypes.byref(g),
+                                              ctypes.byref(u)), "gx_batch_instance_config")
+        return int(b.value), int(g.value), int(u.value)
+
+
+def explore_batch(nets, capacity, stream=None, **opts):
+    """gx_explore_batch: create, run, collect and destroy in one call."""
+    with Batch(nets, capacity, **opts) as b:
+        b.run(stream)
+        return b.results()

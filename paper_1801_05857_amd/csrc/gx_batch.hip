@@ -1,0 +1,594 @@
+// Batched exploration (many networks in one persistent launch per kernel
+// class) and the find-or-put autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "gx_batch_kernel.hpp"
+
+namespace gx {
+
+// implemented in gx_explore.hip
+gx_status compile_network_image(const gx_network* net, std::vector<uint32_t>* img,
+                                uint32_t* words, std::vector<uint32_t>* packed_initial,
+                                uint64_t* max_succ);
+
+// instantiated in gx_batch_s1.hip, gx_batch_s2.hip, gx_batch_s4.hip
+template <int S>
+hipError_t batch_launch(uint32_t B, uint32_t G, uint32_t U, const BatchArgs& a, uint32_t grid,
+                        size_t lds, hipStream_t s);
+template <int S>
+int batch_resident(uint32_t B, uint32_t G, uint32_t U, size_t lds);
+extern template hipError_t batch_launch<1>(uint32_t, uint32_t, uint32_t, const BatchArgs&,
+                                           uint32_t, size_t, hipStream_t);
+extern template hipError_t batch_launch<2>(uint32_t, uint32_t, uint32_t, const BatchArgs&,
+                                           uint32_t, size_t, hipStream_t);
+extern template hipError_t batch_launch<4>(uint32_t, uint32_t, uint32_t, const BatchArgs&,
+                                           uint32_t, size_t, hipStream_t);
+extern template int batch_resident<1>(uint32_t, uint32_t, uint32_t, size_t);
+extern template int batch_resident<2>(uint32_t, uint32_t, uint32_t, size_t);
+extern template int batch_resident<4>(uint32_t, uint32_t, uint32_t, size_t);
+
+namespace {
+
+constexpr uint32_t kDefaultMaxLevels = 4096;
+constexpr uint32_t kQueuePerInstance = 512;
+constexpr uint64_t kSpinLimit = 1ull << 23;  // polls of one to two microseconds each
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- autotuner
+struct TuneKey {
+  uint32_t S;
+  uint32_t load_pct;
+  bool operator<(const TuneKey& o) const { return std::tie(S, load_pct) < std::tie(o.S, o.load_pct); }
+};
+std::map<TuneKey, std::array<uint32_t, 3>> g_tuned;
+std::mutex g_tune_mutex;
+
+__global__ void tune_keys_kernel(uint32_t* keys, uint32_t S, uint64_t n, uint64_t n_distinct,
+                                 uint64_t seed) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // position i holds distinct key (i * odd) mod n_distinct: each key about
+  // n / n_distinct times, far apart in the stream
+  const uint64_t d = (i * 0x9E3779B97F4A7C15ull >> 11) % n_distinct;
+  const uint64_t x = fmix64(d ^ seed);
+  for (uint32_t k = 0; k < S; ++k)
+    keys[i * S + k] = static_cast<uint32_t>((k & 1) ? (x >> 33) : (x & 0x7FFFFFFFu)) ^ k;
+}
+
+}  // namespace
+}  // namespace gx
+
+struct gx_batch {
+  struct Class {
+    uint32_t S = 0, B = 0, G = 0, U = 0;
+    std::vector<uint32_t> members;  // instance ids
+    // device
+    gx::BatchInst* inst = nullptr;
+    gx::BatchState* state = nullptr;
+    gx::BatchState* state_init = nullptr;
+    gx::BatchEntry* queue = nullptr;
+    gx::BatchEntry* queue_init = nullptr;
+    uint32_t queue_cap = 0;
+    gx::BatchGlobal* g = nullptr;
+    gx::BatchGlobal* g_init = nullptr;
+    uint32_t* img = nullptr;
+    uint32_t img_stride = 0;
+    uint32_t* init_states = nullptr;  // n_c x S
+    uint32_t* tables = nullptr;
+    uint64_t table_words = 0;
+    uint32_t* frontiers = nullptr;
+    uint64_t* levels = nullptr;
+    uint32_t* dead = nullptr;
+    uint32_t* dead_tag = nullptr;
+    uint64_t dead_cap = 0;
+    uint64_t* stats = nullptr;
+    uint32_t grid = 0;
+    size_t lds = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_done = nullptr;
+  };
+  int device = 0;
+  uint32_t n = 0;
+  uint32_t max_levels = 0;
+  uint64_t* hc = nullptr;  // hash constants shared by every table
+  uint64_t seed = 0;
+  uint32_t H = 8;
+  std::vector<uint32_t> w, cls;  // per instance: words, class index
+  std::vector<uint32_t> Bi, Gi, Ui;
+  std::vector<Class> classes;
+  hipEvent_t ev_fork = nullptr;
+  bool use_graph = false;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  bool ran = false;
+};
+
+namespace gx {
+namespace {
+
+void free_batch(gx_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  for (auto& c : b->classes) {
+    for (void* p : {static_cast<void*>(c.inst), static_cast<void*>(c.state),
+                    static_cast<void*>(c.state_init), static_cast<void*>(c.queue),
+                    static_cast<void*>(c.queue_init), static_cast<void*>(c.g),
+                    static_cast<void*>(c.g_init), static_cast<void*>(c.img),
+                    static_cast<void*>(c.init_states), static_cast<void*>(c.tables),
+                    static_cast<void*>(c.frontiers), static_cast<void*>(c.levels),
+                    static_cast<void*>(c.dead), static_cast<void*>(c.dead_tag),
+                    static_cast<void*>(c.stats)})
+      if (p) (void)hipFree(p);
+    if (c.side) (void)hipStreamDestroy(c.side);
+    if (c.ev_done) (void)hipEventDestroy(c.ev_done);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->hc) (void)hipFree(b->hc);
+  delete b;
+}
+
+template <typename T>
+hipError_t dmalloc(T** p, uint64_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), std::max<uint64_t>(1, count) * sizeof(T));
+}
+
+// Enqueue one full run of the batch on `stream`: reset every class, then the
+// persistent launch of each class on its own stream, joined back.
+hipError_t enqueue_run(gx_batch* b, hipStream_t stream) {
+  hipError_t e = hipEventRecord(b->ev_fork, stream);
+  if (e != hipSuccess) return e;
+  for (auto& c : b->classes) {
+    const uint32_t nc = static_cast<uint32_t>(c.members.size());
+    if ((e = hipStreamWaitEvent(c.side, b->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = fill_words(c.tables, c.table_words, kEmpty, b->device, c.side)) != hipSuccess) return e;
+    // every queue slot must read "not ready" until a finisher publishes it:
+    // zero the whole queue, then put the initial levels in front
+    if ((e = fill_words(reinterpret_cast<uint32_t*>(c.queue),
+                        static_cast<uint64_t>(c.queue_cap) * (sizeof(BatchEntry) / 4), 0,
+                        b->device, c.side)) != hipSuccess)
+      return e;
+    if ((e = hipMemcpyAsync(c.state, c.state_init, nc * sizeof(BatchState),
+                            hipMemcpyDeviceToDevice, c.side)) != hipSuccess ||
+        (e = hipMemcpyAsync(c.queue, c.queue_init, nc * sizeof(BatchEntry),
+                            hipMemcpyDeviceToDevice, c.side)) != hipSuccess ||
+        (e = hipMemcpyAsync(c.g, c.g_init, sizeof(BatchGlobal), hipMemcpyDeviceToDevice,
+                            c.side)) != hipSuccess)
+      return e;
+    if ((e = fill_words(reinterpret_cast<uint32_t*>(c.stats), 2 * kNumCounters, 0, b->device,
+                        c.side)) != hipSuccess)
+      return e;
+    BatchArgs a;
+    a.inst = c.inst;
+    a.state = c.state;
+    a.queue = c.queue;
+    a.queue_cap = c.queue_cap;
+    a.g = c.g;
+    a.n = nc;
+    a.img = c.img;
+    a.img_stride = c.img_stride;
+    a.dead = c.dead;
+    a.dead_tag = c.dead_tag;
+    a.dead_cap = c.dead_cap;
+    a.spin_limit = kSpinLimit;
+    a.stats = c.stats;
+    a.init_states = c.init_states;
+    switch (c.S) {
+      case 1: e = batch_launch<1>(c.B, c.G, c.U, a, c.grid, c.lds, c.side); break;
+      case 2: e = batch_launch<2>(c.B, c.G, c.U, a, c.grid, c.lds, c.side); break;
+      default: e = batch_launch<4>(c.B, c.G, c.U, a, c.grid, c.lds, c.side); break;
+    }
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(c.ev_done, c.side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(stream, c.ev_done, 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+bool valid_pow2(uint32_t x, uint32_t lo, uint32_t hi) {
+  return x >= lo && x <= hi && (x & (x - 1)) == 0;
+}
+
+}  // namespace
+}  // namespace gx
+
+// ====================================================================== ABI
+extern "C" {
+
+gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
+                      uint32_t* U_out) {
+  if (w < 1 || w > 4 || !(load > 0.0) || load > 0.95 || !B_out || !G_out || !U_out)
+    return GX_EINVAL;
+  const uint32_t S = gx::slot_words(w);
+  const gx::TuneKey key{S, static_cast<uint32_t>(load * 100.0 + 0.5)};
+  std::lock_guard<std::mutex> lock(gx::g_tune_mutex);
+  auto it = gx::g_tuned.find(key);
+  if (it == gx::g_tuned.end()) {
+    // measure every candidate on a synthetic stream: 2^21 keys, each distinct
+    // key about twice, into a table sized for the requested load factor
+    const uint64_t n = 1u << 21, n_distinct = n / 2;
+    uint32_t* keys = nullptr;
+    uint8_t* status = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&keys, n * S * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&status, n) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+      (void)hipGetLastError();
+      if (keys) (void)hipFree(keys);
+      if (status) (void)hipFree(status);
+      return GX_ENOMEM;
+    }
+    hipLaunchKernelGGL(gx::tune_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, nullptr, keys,
+                       S, n, n_distinct, 0x5EEDull);
+    float best = 1e30f;
+    std::array<uint32_t, 3> pick{32, 8, 1};
+    gx_status st = GX_OK;
+    for (uint32_t B : {8u, 16u, 32u, 64u}) {
+      if (B < S * 2) continue;
+      for (uint32_t G : {8u, 16u}) {
+        for (uint32_t U : {1u, 2u}) {
+          gx_table_opts o{0, 64, G, U, 0};
+          gx_table* t = nullptr;
+          if (gx_table_create(S == 4 ? 4 : S, B, static_cast<uint64_t>(n_distinct / load) + 1, &o,
+                              &t) != GX_OK) {
+            st = GX_ENOMEM;
+            continue;
+          }
+          float ms = 0;
+          // warm-up, then the timed insertion into the cleared table
+          (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
+          (void)gx_table_clear(t, nullptr);
+          (void)hipEventRecord(e0, nullptr);
+          (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
+          (void)hipEventRecord(e1, nullptr);
+          if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+              ms < best) {
+            best = ms;
+            pick = {B, G, U};
+          }
+          gx_table_destroy(t);
+        }
+      }
+    }
+    (void)hipFree(keys);
+    (void)hipFree(status);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best >= 1e30f) return st == GX_OK ? GX_EDEVICE : st;
+    it = gx::g_tuned.emplace(key, pick).first;
+  }
+  *B_out = it->second[0];
+  *G_out = it->second[1];
+  *U_out = it->second[2];
+  return GX_OK;
+}
+
+gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opts* opts,
+                          gx_batch** out) {
+  if (!nets || n == 0 || !opts || !opts->capacity || !out) return GX_EINVAL;
+  if (opts->bucket_words && !gx::valid_pow2(opts->bucket_words, 8, 64)) return GX_EINVAL;
+  if (opts->subgroup && !(opts->subgroup == 8 || opts->subgroup == 16)) return GX_EINVAL;
+  if (opts->keys_per_subgroup && !(opts->keys_per_subgroup == 1 || opts->keys_per_subgroup == 2))
+    return GX_EINVAL;
+  // compile every network on the host first: argument errors before device work
+  std::vector<std::vector<uint32_t>> imgs(n), inits(n);
+  std::vector<uint32_t> words(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    uint64_t ms = 0;
+    const gx_status s = gx::compile_network_image(&nets[i], &imgs[i], &words[i], &inits[i], &ms);
+    if (s != GX_OK) return s;
+    if (opts->capacity[i] == 0) return GX_EINVAL;
+  }
+  gx_batch* b = new (std::nothrow) gx_batch;
+  if (!b) return GX_ENOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return GX_EDEVICE;
+  }
+  b->n = n;
+  b->max_levels = opts->max_levels ? opts->max_levels : gx::kDefaultMaxLevels;
+  b->seed = opts->hash_seed ? opts->hash_seed : 0x1801058570ull;
+  b->H = opts->max_hashes ? opts->max_hashes : 8;
+  b->w = words;
+  b->cls.resize(n);
+  b->Bi.resize(n);
+  b->Gi.resize(n);
+  b->Ui.resize(n);
+  // per-instance kernel configuration: explicit, else autotuned for the
+  // instance's slot width at the load factor its capacity is declared for
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t B = opts->bucket_words, G = opts->subgroup, U = opts->keys_per_subgroup;
+    if (!B || !G || !U) {
+      uint32_t tb = 32, tg = 8, tu = 1;
+      const gx_status s = gx_autotune(words[i], 0.5, &tb, &tg, &tu);
+      if (s != GX_OK) {
+        gx::free_batch(b);
+        return s;
+      }
+      B = B ? B : tb;
+      G = G ? G : tg;
+      U = U ? U : tu;
+    }
+    const uint32_t S = gx::slot_words(words[i]);
+    if (B < 2 * S) B = 2 * S;
+    b->Bi[i] = B;
+    b->Gi[i] = G;
+    b->Ui[i] = U;
+    uint32_t k = 0;
+    for (; k < b->classes.size(); ++k) {
+      const auto& c = b->classes[k];
+      if (c.S == S && c.B == B && c.G == G && c.U == U) break;
+    }
+    if (k == b->classes.size()) {
+      b->classes.emplace_back();
+      auto& c = b->classes.back();
+      c.S = S;
+      c.B = B;
+      c.G = G;
+      c.U = U;
+    }
+    b->classes[k].members.push_back(i);
+    b->cls[i] = k;
+  }
+  // shared hash constants
+  std::vector<uint64_t> hc(2 * b->H);
+  for (uint32_t j = 0; j < b->H; ++j) gx::hash_constants(b->seed, j, &hc[2 * j], &hc[2 * j + 1]);
+  if (gx::dmalloc(&b->hc, hc.size()) != hipSuccess ||
+      hipMemcpy(b->hc, hc.data(), hc.size() * sizeof(uint64_t), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
+    gx::free_batch(b);
+    return GX_ENOMEM;
+  }
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  for (auto& c : b->classes) {
+    const uint32_t nc = static_cast<uint32_t>(c.members.size());
+    const uint32_t S = c.S;
+    // layout of the class's tables and frontiers (256-byte aligned pieces)
+    std::vector<uint64_t> tab_off(nc), nb(nc), fr_off(nc);
+    uint64_t tw = 0, fw = 0, imgw = 0, max_img = 0;
+    std::vector<uint64_t> img_off(nc);
+    for (uint32_t k = 0; k < nc; ++k) {
+      const uint32_t i = c.members[k];
+      const uint64_t cap = opts->capacity[i];
+      nb[k] = (cap + c.B / S - 1) / (c.B / S);
+      tab_off[k] = tw;
+      tw += gx::align_up(nb[k] * c.B, 64);
+      fr_off[k] = fw;
+      fw += 2 * gx::align_up(cap * S, 64);
+      img_off[k] = imgw;
+      imgw += imgs[i].size();
+      max_img = std::max<uint64_t>(max_img, imgs[i].size());
+    }
+    c.table_words = tw;
+    c.img_stride = static_cast<uint32_t>(gx::align_up(max_img, 4));
+    c.queue_cap = nc * gx::kQueuePerInstance;
+    uint64_t sum_cap = 0;
+    for (uint32_t i : c.members) sum_cap += opts->capacity[i];
+    c.dead_cap = opts->deadlock_capacity ? opts->deadlock_capacity
+                                         : std::min<uint64_t>(sum_cap, uint64_t(1) << 26);
+    if (gx::dmalloc(&c.tables, tw) != hipSuccess || gx::dmalloc(&c.frontiers, fw) != hipSuccess ||
+        gx::dmalloc(&c.inst, nc) != hipSuccess || gx::dmalloc(&c.state, nc) != hipSuccess ||
+        gx::dmalloc(&c.state_init, nc) != hipSuccess ||
+        gx::dmalloc(&c.queue, c.queue_cap) != hipSuccess ||
+        gx::dmalloc(&c.queue_init, nc) != hipSuccess || gx::dmalloc(&c.g, 1) != hipSuccess ||
+        gx::dmalloc(&c.g_init, 1) != hipSuccess || gx::dmalloc(&c.img, imgw) != hipSuccess ||
+        gx::dmalloc(&c.init_states, static_cast<uint64_t>(nc) * S) != hipSuccess ||
+        gx::dmalloc(&c.levels, static_cast<uint64_t>(nc) * b->max_levels) != hipSuccess ||
+        gx::dmalloc(&c.dead, c.dead_cap * S) != hipSuccess ||
+        gx::dmalloc(&c.dead_tag, c.dead_cap) != hipSuccess ||
+        gx::dmalloc(&c.stats, 2 * gx::kNumCounters) != hipSuccess ||
+        hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c.ev_done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      gx::free_batch(b);
+      return GX_ENOMEM;
+    }
+    std::vector<gx::BatchInst> hi(nc);
+    std::vector<gx::BatchState> hs(nc);
+    std::vector<gx::BatchEntry> he(nc);
+    std::vector<uint32_t> himg(imgw), hinit(static_cast<size_t>(nc) * S, 0);
+    for (uint32_t k = 0; k < nc; ++k) {
+      const uint32_t i = c.members[k];
+      gx::BatchInst& in = hi[k];
+      std::memset(&in, 0, sizeof(in));
+      in.t.words = c.tables + tab_off[k];
+      in.t.n_buckets = nb[k];
+      in.t.hc = b->hc;
+      in.t.seed = b->seed;
+      in.t.a0 = hc[0];
+      in.t.c0 = hc[1];
+      in.t.H = b->H;
+      in.t.counters = c.stats;
+      in.img_off = static_cast<uint32_t>(img_off[k]);
+      in.img_words = static_cast<uint32_t>(imgs[i].size());
+      const uint64_t fcap = gx::align_up(opts->capacity[i] * S, 64);
+      in.f[0] = c.frontiers + fr_off[k];
+      in.f[1] = c.frontiers + fr_off[k] + fcap;
+      in.cap = opts->capacity[i];
+      in.levels = c.levels + static_cast<uint64_t>(k) * b->max_levels;
+      in.max_levels = b->max_levels;
+      std::copy(imgs[i].begin(), imgs[i].end(), himg.begin() + img_off[k]);
+      for (uint32_t x = 0; x < words[i]; ++x) hinit[static_cast<size_t>(k) * S + x] = inits[i][x];
+      std::memset(&hs[k], 0, sizeof(gx::BatchState));
+      hs[k].n_in = 1;
+      std::memset(&he[k], 0, sizeof(gx::BatchEntry));
+      he[k].inst = k;
+      he[k].tiles = 1;
+      he[k].ready = 1;
+    }
+    gx::BatchGlobal hg;
+    std::memset(&hg, 0, sizeof(hg));
+    hg.tail = nc;
+    if (hipMemcpy(c.inst, hi.data(), nc * sizeof(gx::BatchInst), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.state_init, hs.data(), nc * sizeof(gx::BatchState), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c.queue_init, he.data(), nc * sizeof(gx::BatchEntry), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c.g_init, &hg, sizeof(hg), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.img, himg.data(), himg.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c.init_states, hinit.data(), hinit.size() * sizeof(uint32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      gx::free_batch(b);
+      return GX_EDEVICE;
+    }
+    c.lds = (c.img_stride + gx::kStageWords) * sizeof(uint32_t);
+    int per_cu = 1;
+    switch (S) {
+      case 1: per_cu = gx::batch_resident<1>(c.B, c.G, c.U, c.lds); break;
+      case 2: per_cu = gx::batch_resident<2>(c.B, c.G, c.U, c.lds); break;
+      default: per_cu = gx::batch_resident<4>(c.B, c.G, c.U, c.lds); break;
+    }
+    c.grid = static_cast<uint32_t>(per_cu) * static_cast<uint32_t>(cus);
+  }
+  b->use_graph = opts->use_graph != 0;
+  if (b->use_graph) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      gx::free_batch(b);
+      return GX_EDEVICE;
+    }
+    const hipError_t e = gx::enqueue_run(b, b->capture_stream);
+    const hipError_t e2 = hipStreamEndCapture(b->capture_stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess ||
+        hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      gx::free_batch(b);
+      return GX_EDEVICE;
+    }
+    (void)hipGraphDestroy(graph);
+  }
+  *out = b;
+  return GX_OK;
+}
+
+gx_status gx_batch_destroy(gx_batch* b) {
+  gx::free_batch(b);
+  return GX_OK;
+}
+
+gx_status gx_batch_instance_config(const gx_batch* b, uint32_t i, uint32_t* bucket_words,
+                                   uint32_t* subgroup, uint32_t* keys_per_subgroup) {
+  if (!b || i >= b->n || !bucket_words || !subgroup || !keys_per_subgroup) return GX_EINVAL;
+  *bucket_words = b->Bi[i];
+  *subgroup = b->Gi[i];
+  *keys_per_subgroup = b->Ui[i];
+  return GX_OK;
+}
+
+gx_status gx_batch_run(gx_batch* b, void* hip_stream) {
+  if (!b) return GX_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if (b->use_graph) {
+    e = hipGraphLaunch(b->exec, s);
+  } else {
+    e = gx::enqueue_run(b, s);
+  }
+  if (e != hipSuccess) return GX_EDEVICE;
+  b->ran = true;
+  return GX_OK;
+}
+
+gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst_status) {
+  if (!b || !outs || !inst_status || !b->ran) return GX_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return GX_EDEVICE;
+  for (uint32_t i = 0; i < b->n; ++i) {
+    std::memset(&outs[i], 0, sizeof(gx_explore_result));
+    inst_status[i] = GX_EDEVICE;
+  }
+  for (auto& c : b->classes) {
+    const uint32_t nc = static_cast<uint32_t>(c.members.size());
+    const uint32_t S = c.S;
+    std::vector<gx::BatchState> hs(nc);
+    std::vector<uint64_t> lv(static_cast<size_t>(nc) * b->max_levels);
+    gx::BatchGlobal hg;
+    if (hipMemcpy(hs.data(), c.state, nc * sizeof(gx::BatchState), hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(lv.data(), c.levels, lv.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(&hg, c.g, sizeof(hg), hipMemcpyDeviceToHost) != hipSuccess)
+      return GX_EDEVICE;
+    const uint64_t n_rec = std::min<uint64_t>(hg.dead_used, c.dead_cap);
+    std::vector<uint32_t> dead(n_rec * S), tag(n_rec);
+    if (n_rec && (hipMemcpy(dead.data(), c.dead, dead.size() * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost) != hipSuccess ||
+                  hipMemcpy(tag.data(), c.dead_tag, tag.size() * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost) != hipSuccess))
+      return GX_EDEVICE;
+    std::vector<std::vector<std::array<uint32_t, 4>>> per(nc);
+    for (uint64_t r = 0; r < n_rec; ++r) {
+      std::array<uint32_t, 4> v{0, 0, 0, 0};
+      for (uint32_t x = 0; x < S; ++x) v[x] = dead[r * S + x];
+      if (tag[r] < nc) per[tag[r]].push_back(v);
+    }
+    for (uint32_t k = 0; k < nc; ++k) {
+      const uint32_t i = c.members[k];
+      const uint32_t w = b->w[i];
+      const gx::BatchState& st = hs[k];
+      gx_status s = GX_OK;
+      if (!st.done || hg.abort) s = GX_EDEVICE;
+      else if (st.ctr[3] & gx::kFlagTableFull) s = GX_ETABLEFULL;
+      else if (st.ctr[3]) s = GX_ENOMEM;
+      else if (per[k].size() != st.ctr[1]) s = GX_ENOMEM;  // deadlock records overflowed
+      inst_status[i] = s;
+      if (s != GX_OK) continue;
+      const uint32_t n_levels = st.level + 1;
+      uint64_t* L = static_cast<uint64_t*>(std::malloc(sizeof(uint64_t) * n_levels));
+      auto& dl = per[k];
+      std::sort(dl.begin(), dl.end());
+      uint32_t* D = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (dl.size() * w + 1)));
+      if (!L || !D) {
+        std::free(L);
+        std::free(D);
+        inst_status[i] = GX_ENOMEM;
+        continue;
+      }
+      uint64_t total = 0;
+      for (uint32_t l = 0; l < n_levels; ++l) {
+        L[l] = l == 0 ? 1 : lv[static_cast<size_t>(k) * b->max_levels + l];
+        total += L[l];
+      }
+      for (size_t r = 0; r < dl.size(); ++r)
+        for (uint32_t x = 0; x < w; ++x) D[r * w + x] = dl[r][x];
+      outs[i].n_states = total;
+      outs[i].n_transitions = st.ctr[2];
+      outs[i].words_per_state = w;
+      outs[i].n_levels = n_levels;
+      outs[i].level_counts = L;
+      outs[i].n_deadlocks = dl.size();
+      outs[i].deadlocks = D;
+    }
+  }
+  return GX_OK;
+}
+
+gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_opts* opts,
+                           gx_explore_result* outs, gx_status* inst_status) {
+  if (!outs || !inst_status) return GX_EINVAL;
+  gx_batch* b = nullptr;
+  gx_status s = gx_batch_create(nets, n, opts, &b);
+  if (s != GX_OK) return s;
+  s = gx_batch_run(b, opts->hip_stream);
+  if (s == GX_OK) s = gx_batch_results(b, outs, inst_status);
+  gx_batch_destroy(b);
+  return s;
+}
+
+}  // extern "C"

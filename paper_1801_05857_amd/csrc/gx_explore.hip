@@ -174,6 +174,26 @@ gx_status compile_network(const gx_network* net, NetImage* out) {
   return GX_OK;
 }
 
+void pack_host(const NetImage& ni, const uint32_t* local, uint32_t* out);
+
+}  // namespace
+
+gx_status compile_network_image(const gx_network* net, std::vector<uint32_t>* img,
+                                uint32_t* words, std::vector<uint32_t>* packed_initial,
+                                uint64_t* max_succ) {
+  NetImage ni;
+  const gx_status s = compile_network(net, &ni);
+  if (s != GX_OK) return s;
+  packed_initial->assign(4, 0);
+  pack_host(ni, ni.initial.data(), packed_initial->data());
+  *img = std::move(ni.img);
+  *words = ni.words;
+  *max_succ = ni.max_succ;
+  return GX_OK;
+}
+
+namespace {
+
 void pack_host(const NetImage& ni, const uint32_t* local, uint32_t* out) {
   for (uint32_t k = 0; k < ni.words; ++k) out[k] = 0;
   for (size_t p = 0; p < ni.field.size(); ++p) {

@@ -138,101 +138,139 @@ __device__ __forceinline__ void emit_successors(const uint32_t* img, const uint3
   }
 }
 
-// Exclusive prefix sum over the 256 threads; *total receives the sum.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+// Exclusive prefix sum over the 64 lanes of a wavefront; *total receives the
+// wavefront's sum.
+__device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
   const int lane = __lane_id();
-  const int wid = threadIdx.x >> 6;
   uint32_t x = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const uint32_t y = __shfl_up(x, d, 64);
     if (lane >= d) x += y;
   }
-  if (lane == 63) scratch[wid] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t t = scratch[w];
-      scratch[w] = run;
-      run += t;
-    }
-    scratch[4] = run;
-  }
-  __syncthreads();
-  const uint32_t ex = scratch[wid] + x - v;
-  *total = scratch[4];
-  return ex;
+  *total = __shfl(x, 63, 64);
+  return x - v;
 }
 
+// Orders the LDS accesses of one wavefront (its lanes exchange staged
+// successors through LDS; no other wavefront touches that region).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront's share of a BFS level: frontier states [first, first + 64)
+// (those below n_in) of one exploration.  Counters of that exploration:
+// ctr[0] next-frontier tail, ctr[1] deadlocks, ctr[2] transitions, ctr[3] flags.
+struct WaveJob {
+  TableDev t;
+  const uint32_t* img;  // network image, in LDS
+  const uint32_t* frontier_in;
+  uint64_t first, n_in;
+  uint32_t* frontier_out;
+  uint64_t cap_out;
+  uint32_t* dead;       // deadlock states (S words each)
+  uint32_t* dead_tag;   // nullable: per deadlock record, the exploration's tag
+  uint32_t tag;
+  uint64_t dead_cap;
+  uint64_t* dead_ctr;   // deadlock records used (may be shared by explorations)
+  uint64_t* ctr;
+};
+
+// A wavefront owns 64 frontier states and its own slice of the LDS staging
+// buffer, and runs generate -> find-or-put -> append on its own; no barrier
+// couples it to the other wavefronts of its workgroup, so successor
+// generation (ALU) of one wavefront overlaps the table probes (memory) of the
+// others.  Must be reached by the whole wavefront.
 template <int S, int B, int G, int U>
-__global__ __launch_bounds__(256) void explore_level_kernel(ExploreArgs a) {
-  extern __shared__ uint32_t smem[];
-  constexpr int CAP = kStageWords / S;  // staged successors per chunk
-  uint32_t* img = smem;
-  uint32_t* stage = smem + a.img_stride;
-  uint32_t* scratch = stage + kStageWords;
-
-  for (uint32_t i = threadIdx.x; i < a.img_words; i += 256) img[i] = a.img[i];
-  __syncthreads();
-
-  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
-  const bool has = i < a.n_in;
+__device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats& st) {
+  constexpr uint32_t kWaveWords = kStageWords / 4;
+  constexpr uint32_t CAP = kWaveWords / S;  // staged successors per chunk
+  const int lane = __lane_id();
+  const uint64_t i = j.first + lane;
+  const bool has = i < j.n_in;
   uint32_t sw[S];
 #pragma unroll
-  for (int x = 0; x < S; ++x) sw[x] = has ? a.frontier_in[i * S + x] : 0u;
-  const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
+  for (int x = 0; x < S; ++x) sw[x] = has ? j.frontier_in[i * S + x] : 0u;
+  const uint32_t c = has ? count_successors<S>(j.img, sw) : 0u;
   if (has && c == 0) {
-    const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[1]), 1ull);
-    if (d < a.dead_cap) {
+    const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(j.dead_ctr), 1ull);
+    if (j.dead_ctr != &j.ctr[1]) atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[1]), 1ull);
+    if (d < j.dead_cap) {
 #pragma unroll
-      for (int x = 0; x < S; ++x) a.dead[d * S + x] = sw[x];
+      for (int x = 0; x < S; ++x) j.dead[d * S + x] = sw[x];
+      if (j.dead_tag) j.dead_tag[d] = j.tag;
     }
   }
   uint32_t total = 0;
-  const uint32_t off = block_exclusive_scan(c, scratch, &total);
-  if (threadIdx.x == 0 && total)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[2]), static_cast<unsigned long long>(total));
+  const uint32_t off = wave_exclusive_scan(c, &total);
+  if (lane == 0 && total)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[2]), static_cast<unsigned long long>(total));
 
-  const int lane = __lane_id();
-  LaneStats st;
   for (uint32_t lo = 0; lo < total; lo += CAP) {
-    const uint32_t hi = min(total, lo + static_cast<uint32_t>(CAP));
+    const uint32_t hi = min(total, lo + CAP);
     if (c && off < hi && off + c > lo)
-      emit_successors<S>(img, sw, static_cast<int>(lo) - static_cast<int>(off),
+      emit_successors<S>(j.img, sw, static_cast<int>(lo) - static_cast<int>(off),
                          static_cast<int>(hi) - static_cast<int>(off), stage);
-    __syncthreads();
+    wave_lds_sync();
     const uint32_t n_st = hi - lo;
-    for (uint32_t r0 = 0; r0 < n_st; r0 += 256) {
-      const uint32_t idx = r0 + threadIdx.x;
+    for (uint32_t r0 = 0; r0 < n_st; r0 += 64) {
+      const uint32_t idx = r0 + lane;
       const bool act = idx < n_st;
       uint32_t key[S];
 #pragma unroll
       for (int x = 0; x < S; ++x) key[x] = act ? stage[idx * S + x] : 0u;
-      const uint8_t res = find_or_put_lanes<S, B, G, U>(a.t, key, act, st);
+      const uint8_t res = find_or_put_lanes<S, B, G, U>(j.t, key, act, st);
       const bool is_new = act && res == kNew;
       const uint64_t m = __ballot(is_new);
       if (m) {
         unsigned long long base = 0;
         if (lane == 0)
-          base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[0]),
+          base = atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[0]),
                            static_cast<unsigned long long>(__popcll(m)));
         base = __shfl(base, 0, 64);
         if (is_new) {
           const uint64_t pos = base + __popcll(m & ((1ull << lane) - 1ull));
-          if (pos < a.cap_out) {
+          if (pos < j.cap_out) {
 #pragma unroll
-            for (int x = 0; x < S; ++x) a.frontier_out[pos * S + x] = key[x];
+            for (int x = 0; x < S; ++x) j.frontier_out[pos * S + x] = key[x];
           } else {
-            atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
+            atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagFrontierOverflow);
           }
         }
       }
       if (act && res == kFull)
-        atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagTableFull);
+        atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagTableFull);
     }
-    __syncthreads();
+    wave_lds_sync();
   }
+}
+
+// One BFS level of one exploration: 256 frontier states per workgroup.
+template <int S, int B, int G, int U>
+__global__ __launch_bounds__(256) void explore_level_kernel(ExploreArgs a) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* img = smem;
+  uint32_t* stage = smem + a.img_stride + (threadIdx.x >> 6) * (kStageWords / 4);
+  for (uint32_t i = threadIdx.x; i < a.img_words; i += 256) img[i] = a.img[i];
+  __syncthreads();
+  WaveJob j;
+  j.t = a.t;
+  j.img = img;
+  j.frontier_in = a.frontier_in;
+  j.first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
+  j.n_in = a.n_in;
+  j.frontier_out = a.frontier_out;
+  j.cap_out = a.cap_out;
+  j.dead = a.dead;
+  j.dead_tag = nullptr;
+  j.tag = 0;
+  j.dead_cap = a.dead_cap;
+  j.dead_ctr = &a.ctr[1];
+  j.ctr = a.ctr;
+  LaneStats st;
+  if (j.first < j.n_in) expand_wave<S, B, G, U>(j, stage, st);
   flush_stats(a.t, st, nullptr);
 }
 

@@ -79,6 +79,11 @@ extern template hipError_t dispatch_b<4>(uint32_t, uint32_t, uint32_t, const Fop
 hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t n,
                               uint8_t* status, uint64_t* n_new, hipStream_t stream);
 
+// Fill n_words (a multiple of 4, 16-byte aligned) with value, stream-ordered
+// (a kernel, never a memset node, so it may be captured in a graph).
+hipError_t fill_words(uint32_t* p, uint64_t n_words, uint32_t value, int device,
+                      hipStream_t stream);
+
 // Number of workgroups that keep every CU busy for a grid-stride kernel.
 uint32_t resident_grid(int device, uint32_t per_cu);
 

@@ -15,8 +15,9 @@
 namespace gx {
 
 // ------------------------------------------------------------------ kernels
-__global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint64_t* counters) {
-  const uint4 e = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+__global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint32_t value,
+                                                   uint64_t* counters) {
+  const uint4 e = make_uint4(value, value, value, value);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
        i += stride) {
@@ -78,6 +79,18 @@ hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t 
   return hipErrorInvalidValue;
 }
 
+hipError_t fill_words(uint32_t* p, uint64_t n_words, uint32_t value, int device,
+                      hipStream_t stream) {
+  if (n_words == 0) return hipSuccess;
+  const uint64_t n16 = n_words / 4;
+  const uint64_t want = (n16 + 255) / 256;
+  const uint32_t grid = static_cast<uint32_t>(
+      std::max<uint64_t>(1, std::min<uint64_t>(want, resident_grid(device, 8))));
+  hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream, reinterpret_cast<uint4*>(p),
+                     n16, value, static_cast<uint64_t*>(nullptr));
+  return hipGetLastError();
+}
+
 namespace {
 
 hipError_t clear_storage(const gx_table* t, hipStream_t stream) {
@@ -86,7 +99,7 @@ hipError_t clear_storage(const gx_table* t, hipStream_t stream) {
   const uint32_t grid =
       static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(want, resident_grid(t->device, 8))));
   hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream,
-                     reinterpret_cast<uint4*>(t->words), n16, t->counters);
+                     reinterpret_cast<uint4*>(t->words), n16, kEmpty, t->counters);
   return hipGetLastError();
 }
 

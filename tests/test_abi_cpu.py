@@ -155,3 +155,25 @@ def test_hash_family_spreads_keys(lib):
     for i in range(1 << 16):
         loads[gx.hash_bucket([i, 0], 2, 0, 0, nb)] += 1
     assert loads.min() > 0 and loads.max() < 4 * (1 << 16) // nb
+
+
+def test_batch_arguments_rejected_before_device_work(lib):
+    net = W.fig1_producer_consumers()
+    h = gx._NetHolder(net)
+    arr = (gx._Network * 1)(h.c)
+    cap = np.array([0], np.uint64)
+    opts = gx._BatchOpts(cap.ctypes.data, 0, 0, 0, 0, 0, 0, 0, 0, None)
+    out = ctypes.c_void_p()
+    assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    cap[0] = 10
+    opts = gx._BatchOpts(cap.ctypes.data, 0, 0, 12, 0, 0, 0, 0, 0, None)
+    assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._BatchOpts(cap.ctypes.data, 0, 0, 0, 32, 0, 0, 0, 0, None)
+    assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    assert lib.gx_batch_create(arr, 0, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    assert not out.value
+    assert lib.gx_batch_run(None, None) == gx.GX_EINVAL
+    assert lib.gx_batch_results(None, None, None) == gx.GX_EINVAL
+    b = ctypes.c_uint32()
+    assert lib.gx_autotune(0, 0.5, ctypes.byref(b), ctypes.byref(b), ctypes.byref(b)) == gx.GX_EINVAL
+    assert lib.gx_autotune(2, 0.0, ctypes.byref(b), ctypes.byref(b), ctypes.byref(b)) == gx.GX_EINVAL

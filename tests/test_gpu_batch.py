@@ -1,0 +1,109 @@
+"""GPU parity of batched exploration (many networks in one persistent launch
+per kernel class) against the oracle BFS, instance by instance, bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1801_05857_amd as gx
+import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gx.lib()
+    return torch.device("cuda:0")
+
+
+def _mixed_networks(k):
+    nets = [W.fig1_producer_consumers(), W.tiny_cycles(), W.token_ring(5), W.token_ring(11)]
+    for seed in range(k):
+        rng = W.SplitMix64(1000 + seed)
+        P = 3 + rng.below(8)
+        ns = 4 + rng.below(61)
+        live = 2 + rng.below(4)
+        nets.append(W.random_lts(1000 + seed, P, ns, live, 2 + rng.below(2), 32, 0.25,
+                                 0.15 if seed % 3 == 0 else 0.0))
+    return nets
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    nets = _mixed_networks(28)
+    want = [oracle.explore(n) for n in nets]
+    return nets, want
+
+
+def _check(res, want):
+    assert len(res) == len(want)
+    for k, ((st, got), ref) in enumerate(zip(res, want)):
+        assert st == gx.GX_OK, (k, gx.status_str(st))
+        assert got.n_states == ref.n_states, k
+        assert got.levels.tolist() == ref.levels.tolist(), k
+        assert got.n_transitions == ref.n_transitions, k
+        assert np.array_equal(got.deadlocks, ref.deadlocks), k
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_matches_oracle(dev, mixed, use_graph):
+    nets, want = mixed
+    cap = [max(64, 3 * r.n_states) for r in want]
+    with gx.Batch(nets, cap, use_graph=use_graph, max_hashes=32) as b:
+        b.run()
+        _check(b.results(), want)
+        # a second run resets every table and repeats the batch
+        b.run()
+        _check(b.results(), want)
+
+
+@pytest.mark.parametrize("B,G,U", [(8, 8, 1), (16, 16, 2), (64, 8, 2), (32, 16, 1)])
+def test_batch_explicit_configurations(dev, mixed, B, G, U):
+    nets, want = mixed
+    cap = [max(64, 4 * r.n_states) for r in want]
+    res = gx.explore_batch(nets, cap, bucket_words=B, subgroup=G, keys_per_subgroup=U,
+                           max_hashes=64)
+    _check(res, want)
+
+
+def test_batch_equals_single_explorations(dev, mixed):
+    nets, want = mixed
+    cap = [max(64, 3 * r.n_states) for r in want]
+    res = gx.explore_batch(nets, cap, max_hashes=32)
+    for net, (st, got), c in zip(nets, res, cap):
+        B, G, U = 32, 8, 1
+        with gx.Table(gx.network_words(net), B, c, subgroup=G, keys_per_subgroup=U,
+                      max_hashes=32) as t:
+            alone = gx.explore(net, t)
+        assert st == gx.GX_OK
+        assert alone.n_states == got.n_states
+        assert alone.levels.tolist() == got.levels.tolist()
+        assert np.array_equal(alone.deadlocks, got.deadlocks)
+
+
+def test_batch_isolates_a_failing_instance(dev):
+    nets = [W.token_ring(6), W.token_ring(8), W.fig1_producer_consumers()]
+    want = [oracle.explore(n) for n in nets]
+    cap = [3 * want[0].n_states, 64, 64]  # the 34992-state ring gets 64 slots
+    res = gx.explore_batch(nets, cap, max_hashes=4)
+    assert res[0][0] == gx.GX_OK and res[0][1].n_states == want[0].n_states
+    assert res[1][0] == gx.GX_ETABLEFULL and res[1][1] is None
+    assert res[2][0] == gx.GX_OK and res[2][1].n_states == 8
+
+
+def test_batch_of_many_small_instances(dev):
+    nets = [W.random_lts(5000 + s, 4, 8, 3, 2, 16, 0.3, 0.2) for s in range(300)]
+    want = [oracle.explore(n) for n in nets]
+    res = gx.explore_batch(nets, [max(64, 4 * r.n_states) for r in want], max_hashes=32)
+    _check(res, want)
+
+
+def test_autotune_returns_a_valid_configuration(dev):
+    for w in (1, 2, 3):
+        B, G, U = gx.autotune(w, 0.5)
+        assert B in (8, 16, 32, 64) and G in (8, 16) and U in (1, 2)
+        assert gx.autotune(w, 0.5) == (B, G, U)  # cached
