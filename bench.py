@@ -49,6 +49,16 @@ def parse():
     ap.add_argument("--net", action="append", default=[],
                     help="seed:procs:nstates:live:degree:sinkprob (repeatable)")
     ap.add_argument("--cap", type=float, default=1e9, help="table capacity in states (explore)")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched exploration of --batch-n uneven random networks")
+    ap.add_argument("--batch-n", type=int, default=1024)
+    ap.add_argument("--serve", action="store_true",
+                    help="served exploration: Poisson request streams at several rates")
+    ap.add_argument("--serve-n", type=int, default=120, help="requests per rate")
+    ap.add_argument("--dup-sweep", action="store_true",
+                    help="isolated insertion of 2^27 one-word keys at duplication 1..64")
+    ap.add_argument("--token-ring", action="store_true",
+                    help="explore Token Ring instances of 2..16 nodes")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter scale reference)")
     return ap.parse_args()
@@ -154,6 +164,183 @@ def cpu_baseline(target_s: float = 15.0):
                       f"(2^{k} distinct, each twice, shuffled), one thread, {dt:.1f} s"}
 
 
+def run_dup_sweep(gx, torch, W, log2n=27, alpha=0.5):
+    """The isolated insertion experiment of Sec. 5.1 / Fig. 6 at MI355X scale:
+    a stream of 2^27 one-word keys in which every distinct key occurs d times
+    (d = 1 .. 64), inserted into an empty table sized for load factor alpha at
+    the end; bucket of 32 words probed by 32 lanes (the paper's static warp per
+    bucket of 32 integers) against smaller buckets and subgroups (the
+    configurable bucket size, down to 4 words)."""
+    n = 1 << log2n
+    rows = []
+    for dup in (1, 2, 4, 8, 16, 32, 64):
+        keys, _ = W.duplicated_stream_torch(n // dup, dup, SEED, "cuda", w=1)
+        for B, G, U in ((32, 32, 1), (4, 8, 2), (8, 8, 2), (16, 8, 2), (32, 8, 1)):
+            t = gx.Table(1, B, int((n // dup) / alpha) + 1, subgroup=G, keys_per_subgroup=U,
+                         max_hashes=32)
+            st = torch.empty(n, dtype=torch.uint8, device="cuda")
+            t.find_or_put(keys, st)  # warm-up
+            t.clear()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            t.find_or_put(keys, st)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            s = t.stats()
+            rows.append({"duplication": dup, "bucket_words": B, "subgroup": G,
+                         "keys_per_subgroup": U, "ms": round(ms, 3),
+                         "Mops_per_s": round(n / ms / 1e3, 1),
+                         "new": s.stored, "full": s.full})
+            t.close()
+        del keys
+    return rows
+
+
+def run_token_ring(gx, torch, W, sizes=range(2, 17)):
+    """Table 1 (right): Token Ring of N nodes, states and states/s per N."""
+    rows = []
+    for n in sizes:
+        net = W.token_ring(n)
+        states = 2 * n * 3 ** (n - 1)
+        w = gx.network_words(net)
+        t = gx.Table(w, 32, max(64, 2 * states), subgroup=8, keys_per_subgroup=1, max_hashes=16)
+        gx.explore(net, t)  # sizes the resident buffers
+        t.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gx.explore(net, t)
+        dt = time.perf_counter() - t0
+        rows.append({"token_ring_nodes": n, "words": w, "states": r.n_states,
+                     "closed_form": states, "levels": len(r.levels), "seconds": round(dt, 4),
+                     "states_per_s": round(r.n_states / dt)})
+        t.close()
+    return rows
+
+
+def run_batch(gx, torch, W, n, seed=11, hashes=16):
+    """Batched exploration of n uneven random networks: one persistent launch
+    per kernel class replayed from a hipGraph, against one gx_explore call per
+    instance on pre-created tables (both clear their tables and start over)."""
+    nets, caps = W.batch_networks(n, seed)
+    t_setup = time.perf_counter()
+    b = gx.Batch(nets, caps, use_graph=True, max_hashes=hashes)
+    setup_s = time.perf_counter() - t_setup
+    b.run()
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    res = b.results()
+    cfgs = [b.instance_config(i) for i in range(n)]
+    b.close()
+    ok = [r for st, r in res if st == gx.GX_OK]
+    states = sum(r.n_states for r in ok)
+    trans = sum(r.n_transitions for r in ok)
+    t_batch = sorted(runs)[len(runs) // 2]
+    # one exploration per instance, tables and buffers resident
+    tables = [gx.Table(gx.network_words(nt), B, c, subgroup=G, keys_per_subgroup=U,
+                       max_hashes=hashes) for nt, c, (B, G, U) in zip(nets, caps, cfgs)]
+    for nt, t in zip(nets, tables):
+        gx.explore(nt, t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single_states = 0
+    mismatch = 0
+    for k, (nt, t) in enumerate(zip(nets, tables)):
+        t.clear()
+        r = gx.explore(nt, t)
+        single_states += r.n_states
+        st, rb = res[k]
+        if st != gx.GX_OK or rb.n_states != r.n_states or rb.levels.tolist() != r.levels.tolist():
+            mismatch += 1
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    for t in tables:
+        t.close()
+    from collections import Counter
+    return {"batched": {
+        "workload": f"{n} random networks, 3-10 processes of 4-64 states, reachable sizes "
+                    "log-uniform 1e3-1e7 (live-state products), one persistent launch per "
+                    "kernel class from a hipGraph",
+        "instances": n, "ok": len(ok), "states": states, "transitions": trans,
+        "seconds": round(t_batch, 4), "states_per_s": round(states / t_batch),
+        "one_launch_per_instance_seconds": round(t_single, 4),
+        "one_launch_per_instance_states_per_s": round(single_states / t_single),
+        "speedup_vs_one_launch_per_instance": round(t_single / t_batch, 2),
+        "instances_differing_from_single": mismatch,
+        "setup_seconds": round(setup_s, 2),
+        "configs": {f"B{B}-G{G}-U{U}": c for (B, G, U), c in Counter(cfgs).items()}}}
+
+
+def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
+    """Served exploration: Poisson arrivals of requests with reachable sizes
+    spread log-uniformly over 1e4-1.4e8 (token rings of 7-15 nodes, sizes
+    known in closed form) plus three- and four-word random networks; the
+    declared bound is 1.25x the size.  Rates are multiples of the rate at
+    which the server completes them back to back (measured first)."""
+    import random
+
+    rng = random.Random(seed)
+    pool = []
+    for n_nodes in range(7, 16):
+        pool.append((W.token_ring(n_nodes), 2 * n_nodes * 3 ** (n_nodes - 1)))
+    extra = [W.random_lts(303, 12, 64, 3, 3, 32, 0.25, 0.1),
+             W.random_lts(404, 16, 64, 2, 3, 32, 0.25, 0.0)]
+    out = []
+    with gx.Server(200 << 30, max_hashes=16) as srv:
+        # sizes of the random networks, and a warm pool of resident tables
+        for nt in extra:
+            rid = srv.submit(nt, 1 << 20)
+            st, r, _ = srv.poll(rid)
+            pool.append((nt, r.n_states))
+        reqs = [pool[rng.randrange(len(pool))] for _ in range(n_req)]
+        total_states = sum(sz for _, sz in reqs)
+        # back to back, one at a time: the service rate
+        t0 = time.perf_counter()
+        for nt, sz in reqs:
+            srv.poll(srv.submit(nt, int(sz * 1.25)))
+        alone = time.perf_counter() - t0
+        rate_sat = n_req / alone
+        out.append({"served": "one at a time", "requests": n_req, "seconds": round(alone, 3),
+                    "states_per_s": round(total_states / alone)})
+        for mult in rates:
+            lam = mult * rate_sat
+            t_arr = 0.0
+            times = []
+            for _ in range(n_req):
+                t_arr += rng.expovariate(lam)
+                times.append(t_arr)
+            ids = []
+            start = time.perf_counter()
+            for (nt, sz), ta in zip(reqs, times):
+                now = time.perf_counter() - start
+                if ta > now:
+                    time.sleep(ta - now)
+                ids.append(srv.submit(nt, int(sz * 1.25)))
+            lat = []
+            bad = 0
+            for rid, (nt, sz) in zip(ids, reqs):
+                st, r, l = srv.poll(rid)
+                lat.append(l)
+                bad += int(st != gx.GX_OK or r.n_states != sz)
+            wall = time.perf_counter() - start
+            lat.sort()
+            stt = srv.stats()
+            out.append({"served": f"Poisson, rate {mult}x the one-at-a-time rate",
+                        "requests": n_req, "rate_per_s": round(lam, 2),
+                        "seconds": round(wall, 3), "states_per_s": round(total_states / wall),
+                        "p50_latency_s": round(lat[len(lat) // 2], 4),
+                        "p99_latency_s": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
+                        "wrong_results": bad, "active_peak": stt["active_peak"],
+                        "retried": stt["retried"]})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -185,6 +372,22 @@ def main():
             print(json.dumps({"probe_granule_bytes": g, "reads": n_reads, "ms": ms,
                               "Greads_per_s": n_reads / ms / 1e6,
                               "GB_per_s_useful": n_reads * g / ms / 1e6}), flush=True)
+        return
+
+    if args.dup_sweep:
+        for row in run_dup_sweep(gx, torch, W):
+            print(json.dumps(row), flush=True)
+        return
+    if args.token_ring:
+        for row in run_token_ring(gx, torch, W):
+            print(json.dumps(row), flush=True)
+        return
+    if args.batch:
+        print(json.dumps(run_batch(gx, torch, W, args.batch_n)), flush=True)
+        return
+    if args.serve:
+        for row in run_serve(gx, torch, W, args.serve_n):
+            print(json.dumps(row), flush=True)
         return
 
     if args.explore:

@@ -55,8 +55,9 @@ typedef struct gx_table gx_table;
 typedef struct {
   uint64_t hash_seed;  /* seed of the hash-constant sets; 0 picks a fixed default */
   uint32_t max_hashes; /* H, hash functions tried before a key is FULL; 0 -> 8      */
-  uint32_t subgroup;   /* lanes that probe one bucket: 8, 16, 32 or 64; 0 -> the
-                          smaller of bucket_words and 64                         */
+  uint32_t subgroup;   /* lanes that probe one bucket: 8, 16, 32 or 64 (lanes
+                          beyond bucket_words stay idle); 0 -> the larger of 8
+                          and the smaller of bucket_words and 64               */
   uint32_t keys_per_subgroup; /* keys a subgroup keeps in flight: 1, 2, 4 or 8;
                                  0 -> 1                                          */
   uint32_t reserved;
@@ -69,7 +70,8 @@ typedef struct {
  *
  *   words_per_state  w, 1..4.  Each key occupies a slot of S words, S = w for
  *                    w in {1,2,4} and S = 4 for w = 3 (the fourth word is 0).
- *   bucket_words     B, 8, 16, 32 or 64.  A bucket holds B/S slots.
+ *   bucket_words     B, 4, 8, 16, 32 or 64.  A bucket holds B/S slots (a
+ *                    bucket of 4 words holds one 4-word slot).
  *   capacity         number of keys the table must be able to hold; the table
  *                    gets ceil(capacity / (B/S)) buckets (at least 1).
  *   opts             nullable; see gx_table_opts.
@@ -327,6 +329,66 @@ gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_op
  */
 gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bucket_words,
                       uint32_t* subgroup, uint32_t* keys_per_subgroup);
+
+/* ------------------------------------------------------------ serving */
+
+/*
+ * Exploration server.  Requests (a network and a declared bound on its number
+ * of reachable states) are admitted when their HBM reservation fits the
+ * budget: a table with ceil(bound / load_factor) slots rounded up to a power
+ * of two, two frontier buffers and a deadlock buffer of as many states.  An
+ * admitted request takes a resident table from a pool (cleared, never freed
+ * between requests).  A host thread runs steps: one launch per slot width
+ * expands the current BFS level of every admitted request, so requests that
+ * arrive while others run join at the next step (continuous batching).  A
+ * request whose table fills up is retried with twice its bound (up to 6
+ * attempts).  Results equal those of gx_explore on the same network.
+ */
+typedef struct gx_server gx_server;
+
+typedef struct {
+  uint64_t budget_bytes;      /* HBM the server may reserve (tables, frontiers) */
+  uint32_t max_active;        /* requests admitted at once; 0 -> 256           */
+  uint32_t max_hashes;        /* H; 0 -> 8                                     */
+  double load_factor;         /* table load at the declared bound; 0 -> 0.5   */
+  uint64_t hash_seed;         /* 0 -> the default seed                         */
+  uint32_t bucket_words;      /* 0 -> autotuned per slot width, else 8..64     */
+  uint32_t subgroup;          /* 0 -> autotuned, else 8|16                     */
+  uint32_t keys_per_subgroup; /* 0 -> autotuned, else 1|2                      */
+  uint32_t reserved;
+} gx_server_opts;
+
+typedef struct {
+  uint64_t submitted, completed, failed, retried;
+  uint64_t steps;          /* multi-request launches run                        */
+  uint64_t active_peak;    /* largest number of requests admitted at once       */
+  uint64_t reserved_peak;  /* largest reservation held (bytes)                  */
+  uint64_t states;         /* reachable states of completed requests            */
+  uint64_t reserved_now, pooled_bytes, waiting;
+} gx_server_stats;
+
+/* Start a server on the current device (spawns its step thread). */
+gx_status gx_server_create(const gx_server_opts* opts, gx_server** out);
+
+/* Queue a request; the network is compiled and copied before return.
+ * Errors: GX_EINVAL (invalid network, bound 0). */
+gx_status gx_server_submit(gx_server* server, const gx_network* net, uint64_t declared_states,
+                           uint64_t* request_id);
+
+/* Result of a request.  wait = 0: GX_EBUSY while it runs.  On GX_OK the
+ * request's status (GX_OK, GX_ETABLEFULL after the last retry, GX_ENOMEM when
+ * it can never fit the budget, GX_EDEVICE), its result (owned by the caller,
+ * gx_explore_result_free) and its latency from submission to completion are
+ * returned, and the request is forgotten. */
+gx_status gx_server_poll(gx_server* server, uint64_t request_id, int wait,
+                         gx_explore_result* out, gx_status* request_status,
+                         uint64_t* latency_ns);
+
+gx_status gx_server_get_stats(gx_server* server, gx_server_stats* out);
+
+/* Stop the step thread and free everything; no other call on the server may
+ * overlap it. */
+gx_status gx_server_destroy(gx_server* server);
 
 /* ------------------------------------------------------------ measurement */
 

@@ -32,6 +32,8 @@ EXPORTED = [
     "gx_explore_result_free", "gx_status_str", "gx_gather_probe",
     "gx_batch_create", "gx_batch_run", "gx_batch_results", "gx_batch_instance_config",
     "gx_batch_destroy", "gx_explore_batch", "gx_autotune",
+    "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_get_stats",
+    "gx_server_destroy",
 ]
 
 
@@ -92,6 +94,20 @@ class _BatchOpts(ctypes.Structure):
                 ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("max_levels", ctypes.c_uint32),
                 ("deadlock_capacity", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("max_hashes", ctypes.c_uint32), ("load_factor", ctypes.c_double),
+                ("hash_seed", ctypes.c_uint64), ("bucket_words", ctypes.c_uint32),
+                ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "failed", "retried", "steps", "active_peak", "reserved_peak",
+        "states", "reserved_now", "pooled_bytes", "waiting")]
 
 
 _lib_handle = None
@@ -155,6 +171,17 @@ def lib() -> ctypes.CDLL:
         L.gx_autotune.restype = st
         L.gx_autotune.argtypes = [u32, ctypes.c_double, ctypes.POINTER(u32), ctypes.POINTER(u32),
                                   ctypes.POINTER(u32)]
+        L.gx_server_create.restype = st
+        L.gx_server_create.argtypes = [ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)]
+        L.gx_server_submit.restype = st
+        L.gx_server_submit.argtypes = [vp, ctypes.POINTER(_Network), u64, ctypes.POINTER(u64)]
+        L.gx_server_poll.restype = st
+        L.gx_server_poll.argtypes = [vp, u64, ctypes.c_int, ctypes.POINTER(_ExploreResult),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(u64)]
+        L.gx_server_get_stats.restype = st
+        L.gx_server_get_stats.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+        L.gx_server_destroy.restype = st
+        L.gx_server_destroy.argtypes = [vp]
         _lib_handle = L
     return _lib_handle
 
@@ -442,3 +469,57 @@ def explore_batch(nets, capacity, stream=None, **opts):
     with Batch(nets, capacity, **opts) as b:
         b.run(stream)
         return b.results()
+
+
+# ------------------------------------------------------------------ serving
+class Server:
+    """gx_server: admission by HBM reservation, resident tables, continuous
+    batching of exploration requests at BFS-level granularity."""
+
+    def __init__(self, budget_bytes: int, *, max_active: int = 0, max_hashes: int = 0,
+                 load_factor: float = 0.0, hash_seed: int = 0, bucket_words: int = 0,
+                 subgroup: int = 0, keys_per_subgroup: int = 0):
+        opts = _ServerOpts(budget_bytes, max_active, max_hashes, load_factor, hash_seed,
+                           bucket_words, subgroup, keys_per_subgroup, 0)
+        h = ctypes.c_void_p()
+        _check(lib().gx_server_create(ctypes.byref(opts), ctypes.byref(h)), "gx_server_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().gx_server_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, net, declared_states: int) -> int:
+        h = _NetHolder(net)
+        rid = ctypes.c_uint64()
+        _check(lib().gx_server_submit(self._h, ctypes.byref(h.c), declared_states,
+                                      ctypes.byref(rid)), "gx_server_submit")
+        return int(rid.value)
+
+    def poll(self, request_id: int, wait: bool = True):
+        """(status, ExploreResult or None, latency in seconds), or None while
+        the request runs (wait=False)."""
+        res = _ExploreResult()
+        st = ctypes.c_int()
+        lat = ctypes.c_uint64()
+        code = lib().gx_server_poll(self._h, request_id, int(wait), ctypes.byref(res),
+                                    ctypes.byref(st), ctypes.byref(lat))
+        if code == GX_EBUSY:
+            return None
+        _check(code, "gx_server_poll")
+        out = _take_result(res) if st.value == GX_OK else None
+        return int(st.value), out, lat.value * 1e-9
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib().gx_server_get_stats(self._h, ctypes.byref(s)), "gx_server_get_stats")
+        return {n: int(getattr(s, n)) for n, _ in _ServerStats._fields_}

@@ -109,7 +109,7 @@ struct TableDev {
 template <int S, int B, int G>
 struct Geo {
   static_assert(S == 1 || S == 2 || S == 4, "slot words");
-  static_assert(B == 8 || B == 16 || B == 32 || B == 64, "bucket words");
+  static_assert(B == 4 || B == 8 || B == 16 || B == 32 || B == 64, "bucket words");
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "subgroup width");
   static constexpr int GE = G < B ? G : B;          // lanes holding bucket words
   static constexpr int K = B / GE;                  // words per lane

@@ -307,6 +307,7 @@ template <int S>
 hipError_t level_b(uint32_t B, uint32_t G, uint32_t U, const ExploreArgs& a, uint32_t grid,
                    size_t lds, hipStream_t s) {
   switch (B) {
+    case 4: return level_g<S, 4>(G, U, a, grid, lds, s);
     case 8: return level_g<S, 8>(G, U, a, grid, lds, s);
     case 16: return level_g<S, 16>(G, U, a, grid, lds, s);
     case 32: return level_g<S, 32>(G, U, a, grid, lds, s);

@@ -105,6 +105,7 @@ hipError_t dispatch_g(uint32_t G, uint32_t U, const FopArgs& a) {
 template <int S>
 hipError_t dispatch_b(uint32_t B, uint32_t G, uint32_t U, const FopArgs& a) {
   switch (B) {
+    case 4: return dispatch_g<S, 4>(G, U, a);
     case 8: return dispatch_g<S, 8>(G, U, a);
     case 16: return dispatch_g<S, 16>(G, U, a);
     case 32: return dispatch_g<S, 32>(G, U, a);

@@ -144,9 +144,9 @@ const char* gx_status_str(gx_status s) {
 
 gx_status gx_table_create(uint32_t w, uint32_t B, uint64_t capacity, const gx_table_opts* opts,
                           gx_table** out) {
-  if (!out || w < 1 || w > 4 || !gx::pow2_in(B, 8, 64) || capacity == 0) return GX_EINVAL;
+  if (!out || w < 1 || w > 4 || !gx::pow2_in(B, 4, 64) || capacity == 0) return GX_EINVAL;
   const uint32_t S = gx::slot_words(w);
-  uint32_t G = opts && opts->subgroup ? opts->subgroup : std::min<uint32_t>(B, 64);
+  uint32_t G = opts && opts->subgroup ? opts->subgroup : std::max<uint32_t>(8, std::min<uint32_t>(B, 64));
   uint32_t U = opts && opts->keys_per_subgroup ? opts->keys_per_subgroup : 1;
   uint32_t H = opts && opts->max_hashes ? opts->max_hashes : 8;
   uint64_t seed = opts && opts->hash_seed ? opts->hash_seed : 0x1801058570ull;

@@ -47,7 +47,7 @@ def test_status_strings(lib):
 
 
 @pytest.mark.parametrize("w,B,cap,sub,kps", [
-    (0, 32, 10, 0, 0), (5, 32, 10, 0, 0), (1, 12, 10, 0, 0), (1, 4, 10, 0, 0),
+    (0, 32, 10, 0, 0), (5, 32, 10, 0, 0), (1, 12, 10, 0, 0), (1, 2, 10, 0, 0),
     (1, 128, 10, 0, 0), (2, 32, 0, 0, 0), (2, 32, 10, 12, 0), (2, 32, 10, 4, 0),
     (2, 32, 10, 128, 0), (2, 32, 10, 0, 3), (2, 32, 10, 0, 16)])
 def test_table_create_rejects_bad_arguments(lib, w, B, cap, sub, kps):
@@ -177,3 +177,18 @@ def test_batch_arguments_rejected_before_device_work(lib):
     b = ctypes.c_uint32()
     assert lib.gx_autotune(0, 0.5, ctypes.byref(b), ctypes.byref(b), ctypes.byref(b)) == gx.GX_EINVAL
     assert lib.gx_autotune(2, 0.0, ctypes.byref(b), ctypes.byref(b), ctypes.byref(b)) == gx.GX_EINVAL
+
+
+def test_server_arguments_rejected(lib):
+    out = ctypes.c_void_p()
+    assert lib.gx_server_create(None, ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._ServerOpts(0, 0, 0, 0.0, 0, 0, 0, 0, 0)
+    assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._ServerOpts(1 << 20, 0, 0, 0.99, 0, 0, 0, 0, 0)
+    assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._ServerOpts(1 << 20, 0, 0, 0.5, 0, 12, 0, 0, 0)
+    assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    assert not out.value
+    rid = ctypes.c_uint64()
+    assert lib.gx_server_submit(None, None, 10, ctypes.byref(rid)) == gx.GX_EINVAL
+    assert lib.gx_server_destroy(None) == gx.GX_OK

@@ -63,7 +63,7 @@ def test_independent_cycles(dev, sizes):
     _explore_and_compare(W.independent_cycles(sizes), B=16)
 
 
-SPECS = [(B, G) for B in (8, 16, 32, 64) for G in (8, 16, 32, 64)]
+SPECS = [(B, G) for B in (4, 8, 16, 32, 64) for G in (8, 16, 32, 64)]
 
 
 def _net_for_words(w):
@@ -85,10 +85,11 @@ def test_random_networks_every_specialisation(dev, w, B, G):
     assert got.words_per_state == w
 
 
-@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("seed", [2, 8, 11, 13, 14, 20, 24, 25])
 def test_random_networks_with_deadlocks(dev, seed):
-    net = W.random_lts(seed, 5 + seed % 4, 16, 5, 2, 16, 0.3, 0.3)
-    _explore_and_compare(net, B=16, G=16)
+    net = W.random_lts(seed, 3 + seed % 3, 8, 6, 2, 8, 0.5, 0.4)
+    got = _explore_and_compare(net, B=16, G=16)
+    assert got.deadlocks.shape[0] > 0
 
 
 def test_larger_random_network(dev):

@@ -77,7 +77,7 @@ def _placement_ok(table, keys_sorted):
             assert slots[b, s, 3] == 0
 
 
-GRID = [(w, B, G, U) for w in (1, 2, 3, 4) for B in (8, 16, 32, 64) for G in (8, 16, 32, 64)
+GRID = [(w, B, G, U) for w in (1, 2, 3, 4) for B in (4, 8, 16, 32, 64) for G in (8, 16, 32, 64)
         for U in (1, 2, 4, 8)]
 
 

@@ -291,12 +291,15 @@ def _mix62_torch(x):
     return x
 
 
-def duplicated_stream_torch(n_distinct: int, dup: int, seed: int, device):
-    """``duplicated_stream(n_distinct, dup, 2, seed)`` generated with torch on
-    ``device`` (two-word keys, n_distinct * dup a power of two).  Returns the
-    (n, 2) int32 key tensor and the int64 tensor of distinct-key indices per
+def duplicated_stream_torch(n_distinct: int, dup: int, seed: int, device, w: int = 2):
+    """``duplicated_stream(n_distinct, dup, w, seed)`` generated with torch on
+    ``device`` (w = 1 or 2, n_distinct * dup a power of two).  Returns the
+    (n, w) int32 key tensor and the int64 tensor of distinct-key indices per
     position."""
     import torch
+
+    if w not in (1, 2):
+        raise ValueError("one- or two-word keys")
 
     n = n_distinct * dup
     if n & (n - 1):
@@ -315,8 +318,52 @@ def duplicated_stream_torch(n_distinct: int, dup: int, seed: int, device):
         y = y ^ (y >> max(1, bits // 2))
     idx = y % n_distinct
     c = (idx + (seed & MASK62)) & MASK62
+    if w == 1:
+        m31 = (1 << 31) - 1
+        x = c & m31
+        x = (x * 0x2545F491) & m31
+        x = x ^ (x >> 15)
+        x = (x * 0x6F4F2A35) & m31
+        x = x ^ (x >> 13)
+        return x.to(torch.int32).reshape(n, 1), idx
     x = _mix62_torch(c)
     keys = torch.empty((n, 2), dtype=torch.int32, device=device)
     keys[:, 0] = (x & 0x7FFFFFFF).to(torch.int32)
     keys[:, 1] = (x >> 31).to(torch.int32)
     return keys, idx
+
+
+# ------------------------------------------------ batches of uneven networks
+def batch_networks(n: int, seed: int, log10_lo: float = 3.0, log10_hi: float = 7.0,
+                   procs=(3, 10), states=(4, 64), out_degree: int = 3):
+    """n random networks for batched exploration, with uneven sizes.
+
+    Instance i: P ~ U{procs}, declared states n_p ~ U{states} per process, a
+    target T ~ log-uniform [10^lo, 10^hi], and live-state counts m_p (2 <=
+    m_p <= n_p) chosen so that prod m_p is close to 4T.  Every reachable local
+    state is live, so prod m_p bounds the reachable set; it is returned as the
+    instance's capacity.  Returns (networks, capacities).
+    """
+    import math
+
+    rng = SplitMix64(seed)
+    nets, caps = [], []
+    for i in range(n):
+        P = procs[0] + rng.below(procs[1] - procs[0] + 1)
+        ns = [states[0] + rng.below(states[1] - states[0] + 1) for _ in range(P)]
+        u = rng.next() / 2.0**64
+        target = 10 ** (log10_lo + (log10_hi - log10_lo) * u)
+        want = 4.0 * target
+        m = [2] * P
+        # raise the live counts round-robin while the product stays below 4T
+        grew = True
+        while grew:
+            grew = False
+            for p in range(P):
+                if m[p] < ns[p] and math.prod(m) / m[p] * (m[p] + 1) <= want:
+                    m[p] += 1
+                    grew = True
+        nets.append(random_lts(seed * 100003 + i, P, ns, m, out_degree, 32, 0.25, 0.05,
+                               name=f"batch_{seed}_{i}"))
+        caps.append(int(math.prod(m)))
+    return nets, caps
