@@ -137,3 +137,15 @@ def test_word_count_mismatch_rejected(dev):
         with pytest.raises(gx.GxError) as e:
             gx.explore(W.token_ring(4), t)
         assert e.value.code == gx.GX_EINVAL
+
+
+def test_fig1_from_paper_syntax(dev, golden_dir):
+    import os
+
+    from paper_1801_05857_amd import models
+
+    d = os.path.join(golden_dir, "fig1")
+    files = {n: open(os.path.join(d, n)).read() for n in ("producer.aut", "consumer.aut")}
+    net = models.parse_par(open(os.path.join(d, "network.exp")).read(), files)
+    got = _explore_and_compare(net)
+    assert (got.n_states, got.n_transitions) == (8, 24)
