@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--alpha", type=float, default=0.5)
     ap.add_argument("--hashes", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-explore", action="store_true", help="skip the exploration leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--explore", action="store_true",
@@ -162,6 +164,33 @@ def cpu_baseline(target_s: float = 15.0):
     return {"value": round(n / dt / 1e6, 3), "unit": "Mops/s", "cores": 1, "kind": "oracle",
             "sample": f"std::unordered_set insertion of 2^{k + 1} two-word keys "
                       f"(2^{k} distinct, each twice, shuffled), one thread, {dt:.1f} s"}
+
+
+def run_explore_leg(gx, torch, W, spec="1:12:64:6:3:0.17"):
+    """States explored per second on one large random network (12 processes
+    of 64 declared states, 6 live, out-degree 3: 3-word vectors), with the
+    table's buffers resident (a first exploration sizes them)."""
+    seed, P, ns, live, deg, sink = spec.split(":")
+    net = W.random_lts(int(seed), int(P), int(ns), int(live), int(deg), 32, 0.25, float(sink))
+    w = gx.network_words(net)
+    t = gx.Table(w, 32, 1 << 30, subgroup=8, keys_per_subgroup=2, max_hashes=16)
+    gx.explore(net, t)
+    t.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = gx.explore(net, t)
+    dt = time.perf_counter() - t0
+    per_state = r.n_transitions / r.n_states
+    S = t.info.slot_words
+    bps = per_state * max(4 * 32, GRANULE) + 8 * S + GRANULE
+    t.close()
+    return {"workload": f"random network {spec} (seed:procs:states:live:degree:sink), "
+                        f"{w}-word vectors, buckets of 32 words, subgroup 8",
+            "states": r.n_states, "transitions": r.n_transitions, "levels": len(r.levels),
+            "seconds": round(dt, 4), "states_per_s": round(r.n_states / dt),
+            "successors_per_state": round(per_state, 2),
+            "algorithmic_GBps": round(r.n_states * bps / dt / 1e9, 1),
+            "roofline_frac": round(r.n_states * bps / dt / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def run_dup_sweep(gx, torch, W, log2n=27, alpha=0.5):
@@ -501,6 +530,12 @@ def main():
         "find_or_put_Mops_per_s_kernel": round(n / (r["fop_ms"] * 1e-3) / 1e6, 1),
         "clear_ms": round(r["clear_ms"], 4),
     }
+    del keys
+    torch.cuda.empty_cache()
+    if not args.no_explore:
+        out["explore"] = run_explore_leg(gx, torch, W)
+    if not args.no_batch:
+        out.update(run_batch(gx, torch, W, args.batch_n))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

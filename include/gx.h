@@ -217,7 +217,12 @@ typedef struct {
   uint64_t deadlock_capacity; /* largest deadlock count the call may buffer;
                                  0 -> limited by device memory only           */
   void* hip_stream;           /* stream for every launch of the call           */
-  uint32_t reserved[4];
+  uint32_t local_dedup;       /* nonzero: before probing the table, each
+                                 wavefront drops duplicates within its staged
+                                 chunk of successors (the per-block state cache
+                                 of the paper's tool, Sec. 3); results are
+                                 unchanged, table probes fewer                 */
+  uint32_t reserved[3];
 } gx_explore_opts;
 
 typedef struct {
@@ -228,6 +233,8 @@ typedef struct {
   uint64_t* level_counts; /* n_levels entries (library-owned)                  */
   uint64_t n_deadlocks;   /* reachable states without a product transition     */
   uint32_t* deadlocks;    /* n_deadlocks x w words, sorted (library-owned)     */
+  uint64_t local_duplicates; /* successors dropped by the local duplicate
+                                filter (gx_explore with local_dedup), else 0  */
 } gx_explore_result;
 
 /*

@@ -78,14 +78,16 @@ class _Network(ctypes.Structure):
 
 class _ExploreOpts(ctypes.Structure):
     _fields_ = [("frontier_capacity", ctypes.c_uint64), ("deadlock_capacity", ctypes.c_uint64),
-                ("hip_stream", ctypes.c_void_p), ("reserved", ctypes.c_uint32 * 4)]
+                ("hip_stream", ctypes.c_void_p), ("local_dedup", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class _ExploreResult(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_uint64), ("n_transitions", ctypes.c_uint64),
                 ("words_per_state", ctypes.c_uint32), ("n_levels", ctypes.c_uint32),
                 ("level_counts", ctypes.POINTER(ctypes.c_uint64)),
-                ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32))]
+                ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32)),
+                ("local_duplicates", ctypes.c_uint64)]
 
 
 class _BatchOpts(ctypes.Structure):
@@ -372,6 +374,7 @@ class ExploreResult:
     words_per_state: int
     levels: np.ndarray
     deadlocks: np.ndarray
+    local_duplicates: int = 0
 
 
 def _take_result(res: _ExploreResult) -> ExploreResult:
@@ -382,16 +385,17 @@ def _take_result(res: _ExploreResult) -> ExploreResult:
     else:
         dead = np.zeros(0, np.uint32)
     out = ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
-                        dead.reshape(-1, w))
+                        dead.reshape(-1, w), int(res.local_duplicates))
     lib().gx_explore_result_free(ctypes.byref(res))
     return out
 
 
 def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity: int = 0,
-            stream=None) -> ExploreResult:
+            stream=None, local_dedup: bool = False) -> ExploreResult:
     """gx_explore: BFS of the synchronous product into ``table``."""
     h = _NetHolder(net)
-    opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream))
+    opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream),
+                        int(local_dedup))
     res = _ExploreResult()
     _check(lib().gx_explore(ctypes.byref(h.c), table.handle, ctypes.byref(opts),
                             ctypes.byref(res)), "gx_explore")

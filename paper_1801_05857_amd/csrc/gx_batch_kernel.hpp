@@ -194,6 +194,7 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
     j.dead_cap = a.dead_cap;
     j.dead_ctr = &a.g->dead_used;
     j.ctr = bs.ctr;
+    j.dtab = nullptr;
     if (j.first < j.n_in) expand_wave<S, B, G, U>(j, stage, st);
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -353,7 +353,12 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   a.img_words = img_words;
   a.img_stride = img_stride;
   a.ctr = eb.ctr;
-  const size_t lds = (img_stride + gx::kStageWords + 8) * sizeof(uint32_t);
+  a.dedup = opts && opts->local_dedup ? 1u : 0u;
+  const uint32_t dedup_words =
+      a.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
+                                                               : gx::dedup_entries<4>())
+              : 0u;
+  const size_t lds = (img_stride + gx::kStageWords + dedup_words + 8) * sizeof(uint32_t);
   auto read_ctr = [&]() -> gx_status {
     if (hipMemcpyAsync(ctr, eb.ctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
@@ -452,6 +457,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   out->level_counts = lv;
   out->n_deadlocks = n_dead;
   out->deadlocks = dd;
+  out->local_duplicates = ctr[4];
   return GX_OK;
 }
 

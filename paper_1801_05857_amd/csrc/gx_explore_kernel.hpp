@@ -23,10 +23,18 @@ struct ExploreArgs {
   uint64_t cap_out;
   uint32_t* dead;
   uint64_t dead_cap;
-  uint64_t* ctr;  // [0] next-frontier tail [1] deadlocks [2] transitions [3] flags
+  uint64_t* ctr;  // [0] next-frontier tail [1] deadlocks [2] transitions [3] flags [4] local duplicates
+  uint32_t dedup; // nonzero: drop duplicates within each staged chunk before probing
 };
 
 enum : uint32_t { kFlagFrontierOverflow = 1, kFlagTableFull = 2 };
+
+// Per-wavefront LDS hash set of the local duplicate filter: twice as many
+// entries as a chunk holds successors, so it is never more than half full.
+template <int S>
+__host__ __device__ constexpr uint32_t dedup_entries() {
+  return 2u * (kStageWords / 4u / S);
+}
 
 // Field access with mask arithmetic only: a select chain over the words is
 // folded by the compiler into an indexed load from a private array, which
@@ -176,7 +184,18 @@ struct WaveJob {
   uint64_t dead_cap;
   uint64_t* dead_ctr;   // deadlock records used (may be shared by explorations)
   uint64_t* ctr;
+  uint32_t* dtab;       // nullable: this wavefront's LDS duplicate filter
 };
+
+// Hash of a staged successor for the duplicate filter (any mix will do: it
+// only spreads the chunk over the filter's entries).
+template <int S>
+__device__ __forceinline__ uint32_t dedup_hash(const uint32_t (&k)[S]) {
+  uint32_t h = 0x9E3779B9u;
+#pragma unroll
+  for (int x = 0; x < S; ++x) h = (h ^ k[x]) * 0x85EBCA6Bu;
+  return h ^ (h >> 15);
+}
 
 // A wavefront owns 64 frontier states and its own slice of the LDS staging
 // buffer, and runs generate -> find-or-put -> append on its own; no barrier
@@ -215,9 +234,49 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
                          static_cast<int>(hi) - static_cast<int>(off), stage);
     wave_lds_sync();
     const uint32_t n_st = hi - lo;
-    for (uint32_t r0 = 0; r0 < n_st; r0 += 64) {
+    // Local duplicate filter (the block-local state cache of the tool): the
+    // first occurrence of a successor in this chunk claims an entry of the
+    // wavefront's LDS set; later occurrences find it and skip the table
+    // probe (their result would be SEEN).  dupmask bit r: this lane's key of
+    // round r is such a later occurrence.
+    uint32_t dupmask = 0;
+    if (j.dtab) {
+      constexpr uint32_t D = dedup_entries<S>();
+      for (uint32_t e = lane; e < D; e += 64) j.dtab[e] = kEmpty;
+      wave_lds_sync();
+      uint32_t dups = 0;
+      for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
+        const uint32_t idx = r0 + lane;
+        if (idx < n_st) {
+          uint32_t key[S];
+#pragma unroll
+          for (int x = 0; x < S; ++x) key[x] = stage[idx * S + x];
+          uint32_t h = dedup_hash<S>(key) & (D - 1);
+          while (true) {
+            uint32_t prev = kEmpty;
+            if (__hip_atomic_compare_exchange_strong(&j.dtab[h], &prev, idx, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WAVEFRONT))
+              break;  // first occurrence
+            bool same = true;
+#pragma unroll
+            for (int x = 0; x < S; ++x) same &= stage[prev * S + x] == key[x];
+            if (same) {
+              dupmask |= 1u << r;
+              ++dups;
+              break;
+            }
+            h = (h + 1) & (D - 1);
+          }
+        }
+      }
+      const uint32_t wd = wave_sum(dups);
+      if (lane == 0 && wd) atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[4]), wd);
+      wave_lds_sync();
+    }
+    for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
       const uint32_t idx = r0 + lane;
-      const bool act = idx < n_st;
+      const bool act = idx < n_st && !((dupmask >> r) & 1u);
       uint32_t key[S];
 #pragma unroll
       for (int x = 0; x < S; ++x) key[x] = act ? stage[idx * S + x] : 0u;
@@ -269,6 +328,8 @@ __global__ __launch_bounds__(256) void explore_level_kernel(ExploreArgs a) {
   j.dead_cap = a.dead_cap;
   j.dead_ctr = &a.ctr[1];
   j.ctr = a.ctr;
+  j.dtab = a.dedup ? smem + a.img_stride + kStageWords + (threadIdx.x >> 6) * dedup_entries<S>()
+                   : nullptr;
   LaneStats st;
   if (j.first < j.n_in) expand_wave<S, B, G, U>(j, stage, st);
   flush_stats(a.t, st, nullptr);
@@ -276,6 +337,12 @@ __global__ __launch_bounds__(256) void explore_level_kernel(ExploreArgs a) {
 
 template <int S, int B, int G, int U>
 hipError_t launch_level(const ExploreArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
+  if (lds > 65536) {  // more than the default per-workgroup LDS: ask for it
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&explore_level_kernel<S, B, G, U>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((explore_level_kernel<S, B, G, U>), dim3(grid), dim3(256), lds, s, a);
   return hipGetLastError();
 }

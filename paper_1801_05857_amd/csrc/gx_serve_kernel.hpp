@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void serve_step_kernel(ServeArgs a) {
   j.dead_cap = jb.dead_cap;
   j.dead_ctr = &jb.ctr[1];
   j.ctr = jb.ctr;
+  j.dtab = nullptr;
   LaneStats st;
   if (j.first < j.n_in) expand_wave<S, B, G, U>(j, stage, st);
 }

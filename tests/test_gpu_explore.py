@@ -149,3 +149,25 @@ def test_fig1_from_paper_syntax(dev, golden_dir):
     net = models.parse_par(open(os.path.join(d, "network.exp")).read(), files)
     got = _explore_and_compare(net)
     assert (got.n_states, got.n_transitions) == (8, 24)
+
+
+@pytest.mark.parametrize("which", ["tiny", "ring9", "w1", "w2", "w3", "w4"])
+@pytest.mark.parametrize("B,G,U", [(32, 8, 1), (8, 16, 2)])
+def test_local_duplicate_filter_keeps_results(dev, which, B, G, U):
+    net = {"tiny": W.tiny_cycles(), "ring9": W.token_ring(9)}.get(which)
+    if net is None:
+        net = _net_for_words(int(which[1]))
+    want = oracle.explore(net, want_visited=True)
+    with gx.Table(want.words, B, max(64, 2 * want.n_states), subgroup=G, keys_per_subgroup=U,
+                  max_hashes=64) as t:
+        got = gx.explore(net, t, local_dedup=True)
+        assert got.n_states == want.n_states
+        assert got.levels.tolist() == want.levels.tolist()
+        assert got.n_transitions == want.n_transitions
+        assert np.array_equal(got.deadlocks, want.deadlocks)
+        assert np.array_equal(t.dump(), want.visited)
+        s = t.stats()
+        # every successor is either probed or dropped as a local duplicate
+        assert s.lookups + got.local_duplicates == want.n_transitions + 1
+    if which in ("tiny", "ring9"):
+        assert got.local_duplicates > 0
