@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--probe-gib", type=int, action="append", default=[],
+                    help="footprint of the gather probe in GiB (repeatable; default 2)")
     ap.add_argument("--explore", action="store_true",
                     help="explore random networks (see --net) instead of the find-or-put batch")
     ap.add_argument("--net", action="append", default=[],
@@ -385,22 +387,26 @@ def main():
     torch.cuda.set_device(dev)
 
     if args.probe:
-        buf = torch.empty(1 << 29, dtype=torch.int32, device=dev)  # 2 GiB
-        buf.fill_(1)
-        sink = torch.zeros(1, dtype=torch.int64, device=dev)
-        for g in (4, 8, 16, 32, 64, 128, 256):
-            n_reads = (1 << 31) // g if g >= 64 else (1 << 26)
-            gx.gather_probe(buf, g, n_reads, 7, sink)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            gx.gather_probe(buf, g, n_reads, 7, sink)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            print(json.dumps({"probe_granule_bytes": g, "reads": n_reads, "ms": ms,
-                              "Greads_per_s": n_reads / ms / 1e6,
-                              "GB_per_s_useful": n_reads * g / ms / 1e6}), flush=True)
+        for gib in args.probe_gib or [2]:
+            buf = torch.empty(gib << 28, dtype=torch.int32, device=dev)
+            buf.fill_(1)
+            sink = torch.zeros(1, dtype=torch.int64, device=dev)
+            for g in (4, 8, 16, 32, 64, 128, 256):
+                n_reads = (1 << 31) // g if g >= 64 else (1 << 26)
+                gx.gather_probe(buf, g, n_reads, 7, sink)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                gx.gather_probe(buf, g, n_reads, 7, sink)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                print(json.dumps({"footprint_GiB": gib, "probe_granule_bytes": g,
+                                  "reads": n_reads, "ms": ms,
+                                  "Greads_per_s": n_reads / ms / 1e6,
+                                  "GB_per_s_useful": n_reads * g / ms / 1e6}), flush=True)
+            del buf
+            torch.cuda.empty_cache()
         return
 
     if args.dup_sweep:

@@ -348,8 +348,9 @@ gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bu
  * between requests).  A host thread runs steps: one launch per slot width
  * expands the current BFS level of every admitted request, so requests that
  * arrive while others run join at the next step (continuous batching).  A
- * request whose table fills up is retried with twice its bound (up to 6
- * attempts).  Results equal those of gx_explore on the same network.
+ * request whose table fills up is retried with four times its bound (at
+ * least twice the states found before it filled up; up to 12 attempts, and
+ * only while the reservation fits the budget).  Results equal those of gx_explore on the same network.
  */
 typedef struct gx_server gx_server;
 

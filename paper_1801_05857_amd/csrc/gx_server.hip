@@ -3,7 +3,7 @@
 // from a pool (cleared, never freed between requests), and are advanced one
 // BFS level per step by a multi-job launch over every active request
 // (continuous batching: requests join and leave between steps).  A request
-// whose table fills up is retried with twice the reservation.
+// whose table fills up is retried with four times its bound.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,7 +40,7 @@ extern template hipError_t serve_launch<4>(uint32_t, uint32_t, uint32_t, const S
 namespace {
 
 using Clock = std::chrono::steady_clock;
-constexpr uint32_t kMaxAttempts = 6;
+constexpr uint32_t kMaxAttempts = 12;
 
 struct Request {
   uint64_t id = 0;
@@ -262,7 +262,10 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
   Request* r = j.r;
   if (st == GX_ETABLEFULL && r->attempts + 1 < kMaxAttempts) {
     ++r->attempts;
-    r->declared *= 2;
+    // four times the bound, and at least twice the states already found
+    uint64_t found = 0;
+    for (uint64_t c : j.levels) found += c;
+    r->declared = std::max<uint64_t>(r->declared * 4, 2 * found);
     ++s->stats.retried;
     s->waiting.push_front(r);
   } else if (st != GX_OK) {

@@ -82,6 +82,7 @@ hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t 
 hipError_t fill_words(uint32_t* p, uint64_t n_words, uint32_t value, int device,
                       hipStream_t stream) {
   if (n_words == 0) return hipSuccess;
+  if (n_words % 4) return hipErrorInvalidValue;  // written as 16-byte vectors
   const uint64_t n16 = n_words / 4;
   const uint64_t want = (n16 + 255) / 256;
   const uint32_t grid = static_cast<uint32_t>(
