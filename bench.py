@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--net", action="append", default=[],
                     help="seed:procs:nstates:live:degree:sinkprob (repeatable)")
     ap.add_argument("--cap", type=float, default=1e9, help="table capacity in states (explore)")
+    ap.add_argument("--local-dedup", action="store_true",
+                    help="explore with the per-wavefront duplicate filter")
     ap.add_argument("--batch", action="store_true",
                     help="batched exploration of --batch-n uneven random networks")
     ap.add_argument("--batch-n", type=int, default=1024)
@@ -438,12 +440,12 @@ def main():
             try:
                 # first run: sizes the table-resident buffers; the timed run
                 # explores into the cleared table with every buffer resident
-                gx.explore(net, t)
+                gx.explore(net, t, local_dedup=args.local_dedup)
                 cold = time.perf_counter() - t0
                 t.clear()
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                r = gx.explore(net, t)
+                r = gx.explore(net, t, local_dedup=args.local_dedup)
                 dt = time.perf_counter() - t0
                 s = t.stats()
                 per_state = (r.n_transitions / max(1, r.n_states))
@@ -457,7 +459,10 @@ def main():
                                   "succ_per_state": round(per_state, 2),
                                   "probes_per_lookup": round(s.probes / max(1, s.lookups), 4),
                                   "algo_GBps": round(r.n_states * bps / dt / 1e9, 1),
-                                  "load": round(r.n_states / t.info.n_slots, 3)}), flush=True)
+                                  "load": round(r.n_states / t.info.n_slots, 3),
+                                  "B": args.bucket, "G": args.subgroup, "U": args.kps,
+                                  "local_dedup": args.local_dedup,
+                                  "local_duplicates": r.local_duplicates}), flush=True)
             except gx.GxError as e:
                 print(json.dumps({"net": spec, "error": str(e),
                                   "seconds": round(time.perf_counter() - t0, 3)}), flush=True)
