@@ -89,6 +89,10 @@ def _load():
         lib.oracle_bruteforce.restype = i32
         lib.oracle_bruteforce.argtypes = net_args + [i32, ctypes.POINTER(_Result)]
         lib.oracle_result_free.argtypes = [ctypes.POINTER(_Result)]
+        lib.oracle_successors.restype = i32
+        lib.oracle_successors.argtypes = net_args + [vp, u64, vp, ctypes.POINTER(vp),
+                                                     ctypes.POINTER(u64)]
+        lib.oracle_free.argtypes = [vp]
         _lib = lib
     return _lib
 
@@ -201,6 +205,29 @@ def bruteforce(net, want_visited: bool = False) -> OracleResult:
     if rc == -2:
         raise OverflowError("product of local state counts exceeds 2^24")
     return _collect(res, want_visited)
+
+
+def successors(net, states) -> tuple[np.ndarray, np.ndarray]:
+    """Product successors (Sec. 3) of packed states (n x words), with
+    multiplicity: (counts (n,), successors (sum(counts), words)), the
+    successors of state i at rows sum(counts[:i]) ... in listing order."""
+    args, keep = _flatten(net)
+    words = pack_plan(net.n_states)[0]
+    st = np.ascontiguousarray(states, dtype=np.uint32).reshape(-1, words)
+    counts = np.zeros(st.shape[0], dtype=np.uint64)
+    out = ctypes.c_void_p()
+    n_out = ctypes.c_uint64()
+    lib = _load()
+    rc = lib.oracle_successors(*args, _ptr(st), st.shape[0], _ptr(counts), ctypes.byref(out),
+                               ctypes.byref(n_out))
+    del keep
+    if rc != 0:
+        raise ValueError("invalid network or state")
+    n = int(n_out.value)
+    buf = (ctypes.c_uint32 * max(1, n * words)).from_address(out.value)
+    succ = np.frombuffer(buf, dtype=np.uint32, count=n * words).copy().reshape(n, words)
+    lib.oracle_free(out)
+    return counts, succ
 
 
 def pack_plan(n_states) -> tuple[int, np.ndarray, np.ndarray, np.ndarray]:

@@ -396,6 +396,45 @@ int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial
   return 0;
 }
 
+// Product successors (Sec. 3), with multiplicity, of n packed states
+// (n x words).  counts[i] receives the number of successors of state i; *out
+// receives a malloc'd array of all successors, packed, state by state in the
+// order successors() lists them (free with oracle_free).  Returns 0, or -1 on
+// an invalid network or a state with a field outside its process's states.
+int oracle_successors(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                      const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                      const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
+                      const uint32_t* states, uint64_t n, uint64_t* counts, uint32_t** out,
+                      uint64_t* n_out) {
+  Net net;
+  Plan plan;
+  if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
+                          &net))
+    return -1;
+  if (!make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
+  std::vector<uint32_t> all;
+  std::vector<std::vector<uint32_t>> succ;
+  for (uint64_t i = 0; i < n; ++i) {
+    Vec v{};
+    for (uint32_t k = 0; k < plan.words; ++k) v[k] = states[i * plan.words + k];
+    std::vector<uint32_t> local = unpack(plan, v);
+    for (uint32_t p = 0; p < P; ++p)
+      if (local[p] >= n_states[p]) return -1;
+    successors(net, local, &succ);
+    counts[i] = succ.size();
+    for (const auto& t : succ) {
+      Vec w = pack(plan, t);
+      for (uint32_t k = 0; k < plan.words; ++k) all.push_back(w[k]);
+    }
+  }
+  *n_out = all.size() / plan.words;
+  *out = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (all.size() + 1)));
+  std::copy(all.begin(), all.end(), *out);
+  return 0;
+}
+
+void oracle_free(void* p) { std::free(p); }
+
 // Brute-force fixpoint over a dense bitmap of every vector of local states
 // (mixed-radix index over n_p), a different algorithm and data structure from
 // the BFS above: R_0 = {init}, R_{k+1} = R_k  union  post(R_k), recomputing post of

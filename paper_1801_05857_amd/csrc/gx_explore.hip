@@ -219,9 +219,10 @@ hipError_t launch_level_any(const gx_table* t, const ExploreArgs& a, uint32_t gr
 // Grow a device buffer of `cap` elements of `elem` bytes to at least `need`
 // elements, keeping its first `keep` elements.  Waits for the stream first.
 hipError_t grow(void** p, uint64_t* cap, uint64_t need, size_t elem, uint64_t keep,
-                hipStream_t stream) {
+                hipStream_t stream, uint64_t limit) {
   if (*cap >= need && *p) return hipSuccess;
-  uint64_t nc = std::max<uint64_t>(need, *cap + *cap / 2);
+  // at least half again the old size (amortised growth), never above limit
+  const uint64_t nc = std::max<uint64_t>(need, std::min<uint64_t>(limit, *cap + *cap / 2));
   void* q = nullptr;
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return e;
@@ -304,7 +305,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     if (need > limit) return GX_ENOMEM;
     const uint64_t want = std::min<uint64_t>(limit, std::max<uint64_t>(need, 1u << 16));
     const hipError_t e = gx::grow(reinterpret_cast<void**>(p), cap, want, state_bytes, keep,
-                                  stream);
+                                  stream, limit);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GX_ENOMEM;
     return e == hipSuccess ? GX_OK : GX_EDEVICE;
   };
@@ -314,7 +315,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   const uint32_t img_stride = (img_words + 3) & ~3u;
   if (eb.img_cap < img_stride) {
     if (gx::grow(reinterpret_cast<void**>(&eb.img), &eb.img_cap, img_stride, sizeof(uint32_t), 0,
-                 stream) != hipSuccess)
+                 stream, img_stride) != hipSuccess)
       return GX_ENOMEM;
   }
   if (!eb.ctr && (hipMalloc(&eb.ctr, 8 * sizeof(uint64_t)) != hipSuccess ||
@@ -369,47 +370,60 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   };
 
   // Levels are expanded in slices small enough that even if every successor
-  // were new the next frontier (and the deadlock list) could not overflow:
-  // slice * max_succ <= free frontier room.  The exact fill is read back only
-  // when the room runs out; then the buffer grows (keeping its contents).
+  // were new the next frontier could not overflow: slice * max_succ <= free
+  // frontier room (and slice <= free deadlock room, one record per state at
+  // most).  The room is tracked from these worst-case bounds; only when it is
+  // short of a full slice is the exact fill read back (one synchronisation),
+  // and the buffers grow, keeping their contents, to hold a full slice.
   std::vector<uint64_t> levels{1};
   uint64_t n_in = 1;
   int cur = 0;
   uint64_t dead_known = 0;
-  constexpr uint64_t kTargetSlice = 1u << 20;
+  constexpr uint64_t kTargetSlice = 1u << 22;  // 16384 workgroups per launch
+  constexpr uint64_t kMaxRoom = 1ull << 28;    // states of frontier room one slice may claim
   while (n_in > 0) {
     const int nxt = cur ^ 1;
     if (hipMemsetAsync(eb.ctr, 0, sizeof(uint64_t), stream) != hipSuccess) return GX_EDEVICE;
     uint64_t tail_known = 0, bound = 0, dead_bound = dead_known, pos = 0;
     while (pos < n_in) {
-      uint64_t slice = std::min<uint64_t>(n_in - pos, (eb.f_cap[nxt] - bound) / max_succ);
-      slice = std::min<uint64_t>(slice, eb.dead_cap - dead_bound);
-      if (slice == 0) {
-        if ((s = read_ctr()) != GX_OK) return s;
-        tail_known = bound = ctr[0];
-        dead_known = dead_bound = ctr[1];
-        const uint64_t want = std::min<uint64_t>(n_in - pos, kTargetSlice);
-        if (eb.f_cap[nxt] - bound < max_succ) {
-          s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], tail_known + want * max_succ, tail_known,
-                       max_cap);
-          if (s == GX_ENOMEM && tail_known + max_succ <= max_cap)
-            s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], max_cap, tail_known, max_cap);
+      // full slices, but never more than kMaxRoom states of frontier room
+      const uint64_t want = std::min<uint64_t>(
+          n_in - pos, std::min<uint64_t>(kTargetSlice, std::max<uint64_t>(1, kMaxRoom / max_succ)));
+      // usable capacities: a buffer left larger by an earlier call still
+      // honours this call's limits
+      auto f_cap = [&]() { return std::min<uint64_t>(eb.f_cap[nxt], max_cap); };
+      auto d_cap = [&]() { return std::min<uint64_t>(eb.dead_cap, max_dead); };
+      auto f_room = [&]() { return (f_cap() - bound) / max_succ; };
+      // a deadlock buffer at its limit no longer bounds the slice: records
+      // past it are counted, not stored, and the call ends with GX_ENOMEM
+      auto d_room = [&]() { return d_cap() >= max_dead ? ~0ull : d_cap() - dead_bound; };
+      if (std::min<uint64_t>(f_room(), d_room()) < want) {
+        if (bound != tail_known || dead_bound != dead_known) {
+          if ((s = read_ctr()) != GX_OK) return s;
+          tail_known = bound = ctr[0];
+          dead_known = dead_bound = ctr[1];
+        }
+        if (f_room() < want) {
+          s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], bound + want * max_succ, tail_known, max_cap);
+          if (s == GX_ENOMEM)  // no room for a full slice: settle for one state
+            s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], bound + max_succ, tail_known,
+                         std::min<uint64_t>(max_cap, bound + max_succ));
           if (s != GX_OK) return s;
         }
-        if (eb.dead_cap - dead_bound < 1) {
-          s = grow_buf(&eb.dead, &eb.dead_cap, dead_known + want, dead_known, max_dead);
-          if (s == GX_ENOMEM && dead_known < max_dead)
-            s = grow_buf(&eb.dead, &eb.dead_cap, max_dead, dead_known, max_dead);
+        if (d_room() < want) {
+          s = grow_buf(&eb.dead, &eb.dead_cap, std::min<uint64_t>(dead_bound + want, max_dead),
+                       std::min<uint64_t>(dead_known, eb.dead_cap), max_dead);
           if (s != GX_OK) return s;
         }
-        continue;
       }
+      const uint64_t slice = std::min<uint64_t>(want, std::min<uint64_t>(f_room(), d_room()));
+      if (slice == 0) return GX_ENOMEM;
       a.frontier_in = eb.f[cur] + pos * S;
       a.n_in = slice;
       a.frontier_out = eb.f[nxt];
-      a.cap_out = eb.f_cap[nxt];
+      a.cap_out = f_cap();
       a.dead = eb.dead;
-      a.dead_cap = eb.dead_cap;
+      a.dead_cap = d_cap();
       const uint64_t grid = (slice + 255) / 256;
       if (gx::launch_level_any(t, a, static_cast<uint32_t>(grid), lds, stream) != hipSuccess)
         return GX_EDEVICE;
@@ -424,7 +438,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     cur = nxt;
   }
   const uint64_t n_dead = ctr[1];
-  if (n_dead > eb.dead_cap) return GX_ENOMEM;
+  if (n_dead > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;
   std::vector<uint32_t> raw(n_dead * S);
   if (n_dead && hipMemcpy(raw.data(), eb.dead, raw.size() * sizeof(uint32_t),
                           hipMemcpyDeviceToHost) != hipSuccess)

@@ -233,3 +233,40 @@ def test_duplicated_stream_shape():
     uniq, counts = np.unique(ks, axis=0, return_counts=True)
     assert uniq.shape[0] == 1000 and (counts == 3).all()
     assert not (ks == 0xFFFFFFFF).any()
+
+
+def test_fig1_successors_by_hand():
+    """oracle.successors against successor multisets derived by hand from
+    Fig. 1 (tests/golden/fig1_successors.txt)."""
+    net = W.fig1_producer_consumers()
+    rows = []
+    for line in open(os.path.join(GOLDEN, "fig1_successors.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        state, succ = line.split(":")
+        rows.append((int(state, 16), sorted(int(x, 16) for x in succ.split())))
+    counts, succ = oracle.successors(net, np.array([[s] for s, _ in rows], dtype=np.uint32))
+    assert counts.tolist() == [len(want) for _, want in rows]
+    at = 0
+    for (_, want), c in zip(rows, counts):
+        assert sorted(succ[at:at + int(c), 0].tolist()) == want
+        at += int(c)
+
+
+def test_successor_counts_sum_to_transitions():
+    """Over the reachable set, successor counts add up to the transition count
+    of the BFS, and the successors of the deadlocks are empty (random networks
+    with deadlocks, and the Token Ring)."""
+    for net in [W.random_lts(s, 3 + s % 3, 8, 6, 2, 8, 0.5, 0.4) for s in (2, 8, 13)] + \
+            [W.token_ring(5)]:
+        r = oracle.explore(net, want_visited=True)
+        counts, succ = oracle.successors(net, r.visited)
+        assert int(counts.sum()) == r.n_transitions
+        assert succ.shape[0] == r.n_transitions
+        if len(r.deadlocks):
+            dc, _ = oracle.successors(net, r.deadlocks)
+            assert (dc == 0).all()
+        # closure: every successor is in the reachable set
+        vis = {tuple(v) for v in r.visited.tolist()}
+        assert all(tuple(v) in vis for v in succ.tolist())
