@@ -27,12 +27,15 @@
 
 namespace gx {
 // instantiated in gx_explore_s1.hip, gx_explore_s2.hip and gx_explore_s4.hip
-extern template hipError_t level_b<1>(uint32_t, uint32_t, uint32_t, const ExploreArgs&,
-                                      uint32_t, size_t, hipStream_t);
-extern template hipError_t level_b<2>(uint32_t, uint32_t, uint32_t, const ExploreArgs&,
-                                      uint32_t, size_t, hipStream_t);
-extern template hipError_t level_b<4>(uint32_t, uint32_t, uint32_t, const ExploreArgs&,
-                                      uint32_t, size_t, hipStream_t);
+extern template hipError_t launch_gen<1>(const GenArgs&, uint32_t, size_t, hipStream_t);
+extern template hipError_t launch_gen<2>(const GenArgs&, uint32_t, size_t, hipStream_t);
+extern template hipError_t launch_gen<4>(const GenArgs&, uint32_t, size_t, hipStream_t);
+extern template hipError_t append_b<1>(uint32_t, uint32_t, uint32_t, const AppendArgs&, uint32_t,
+                                       hipStream_t);
+extern template hipError_t append_b<2>(uint32_t, uint32_t, uint32_t, const AppendArgs&, uint32_t,
+                                       hipStream_t);
+extern template hipError_t append_b<4>(uint32_t, uint32_t, uint32_t, const AppendArgs&, uint32_t,
+                                       hipStream_t);
 }  // namespace gx
 
 namespace gx {
@@ -206,12 +209,21 @@ void pack_host(const NetImage& ni, const uint32_t* local, uint32_t* out) {
 
 namespace {
 
-hipError_t launch_level_any(const gx_table* t, const ExploreArgs& a, uint32_t grid, size_t lds,
-                            hipStream_t s) {
+// One slice of a level: successor generation, then find-or-put-and-append.
+hipError_t launch_slice(const gx_table* t, const GenArgs& g, uint32_t grid, size_t lds,
+                        const AppendArgs& ap, uint32_t cus, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(g.ctr + 5, 0, sizeof(uint64_t), s);
+  if (e != hipSuccess) return e;
   switch (t->S) {
-    case 1: return level_b<1>(t->B, t->G, t->U, a, grid, lds, s);
-    case 2: return level_b<2>(t->B, t->G, t->U, a, grid, lds, s);
-    case 4: return level_b<4>(t->B, t->G, t->U, a, grid, lds, s);
+    case 1:
+      if ((e = launch_gen<1>(g, grid, lds, s)) != hipSuccess) return e;
+      return append_b<1>(t->B, t->G, t->U, ap, cus, s);
+    case 2:
+      if ((e = launch_gen<2>(g, grid, lds, s)) != hipSuccess) return e;
+      return append_b<2>(t->B, t->G, t->U, ap, cus, s);
+    case 4:
+      if ((e = launch_gen<4>(g, grid, lds, s)) != hipSuccess) return e;
+      return append_b<4>(t->B, t->G, t->U, ap, cus, s);
   }
   return hipErrorInvalidValue;
 }
@@ -348,18 +360,25 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   if (st0 == gx::kFull) return GX_ETABLEFULL;
   if (st0 != gx::kNew) return GX_EINVAL;
 
-  gx::ExploreArgs a;
-  a.t = t->dev();
-  a.img = eb.img;
-  a.img_words = img_words;
-  a.img_stride = img_stride;
-  a.ctr = eb.ctr;
-  a.dedup = opts && opts->local_dedup ? 1u : 0u;
+  gx::GenArgs g;
+  g.img = eb.img;
+  g.img_words = img_words;
+  g.img_stride = img_stride;
+  g.ctr = eb.ctr;
+  g.dedup = opts && opts->local_dedup ? 1u : 0u;
+  gx::AppendArgs ap;
+  ap.t = t->dev();
+  ap.keys = nullptr;
+  ap.n_keys = eb.ctr + 5;
+  ap.ctr = eb.ctr;
   const uint32_t dedup_words =
-      a.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
+      g.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
                                                                : gx::dedup_entries<4>())
               : 0u;
-  const size_t lds = (img_stride + gx::kStageWords + dedup_words + 8) * sizeof(uint32_t);
+  const size_t lds =
+      (img_stride + (g.dedup ? gx::kStageWords + dedup_words : 0u) + 8) * sizeof(uint32_t);
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
   auto read_ctr = [&]() -> gx_status {
     if (hipMemcpyAsync(ctr, eb.ctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
@@ -418,18 +437,33 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       }
       const uint64_t slice = std::min<uint64_t>(want, std::min<uint64_t>(f_room(), d_room()));
       if (slice == 0) return GX_ENOMEM;
-      a.frontier_in = eb.f[cur] + pos * S;
-      a.n_in = slice;
-      a.frontier_out = eb.f[nxt];
-      a.cap_out = f_cap();
-      a.dead = eb.dead;
-      a.dead_cap = d_cap();
-      const uint64_t grid = (slice + 255) / 256;
-      if (gx::launch_level_any(t, a, static_cast<uint32_t>(grid), lds, stream) != hipSuccess)
+      // the slice's successors (all of them, in the worst case) fit the
+      // successor buffer
+      const uint64_t slice_keys = slice * max_succ;
+      if (eb.succ_cap < slice_keys) {
+        s = grow_buf(&eb.succ, &eb.succ_cap, slice_keys, 0, ~0ull);
+        if (s == GX_ENOMEM)  // settle for what fits, at least one state
+          s = grow_buf(&eb.succ, &eb.succ_cap, max_succ, 0, ~0ull);
+        if (s != GX_OK) return s;
+      }
+      const uint64_t run = std::min<uint64_t>(slice, eb.succ_cap / max_succ);
+      g.frontier_in = eb.f[cur] + pos * S;
+      g.n_in = run;
+      g.succ = eb.succ;
+      g.succ_cap = eb.succ_cap;
+      g.dead = eb.dead;
+      g.dead_cap = d_cap();
+      ap.keys = eb.succ;
+      ap.keys_cap = eb.succ_cap;
+      ap.frontier_out = eb.f[nxt];
+      ap.cap_out = f_cap();
+      const uint64_t grid = (run + 255) / 256;
+      if (gx::launch_slice(t, g, static_cast<uint32_t>(grid), lds, ap, static_cast<uint32_t>(cus),
+                           stream) != hipSuccess)
         return GX_EDEVICE;
-      pos += slice;
-      bound += slice * max_succ;
-      dead_bound += slice;
+      pos += run;
+      bound += run * max_succ;
+      dead_bound += run;
     }
     if ((s = read_ctr()) != GX_OK) return s;
     dead_known = ctr[1];

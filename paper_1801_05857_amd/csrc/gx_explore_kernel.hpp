@@ -12,20 +12,6 @@ constexpr uint32_t kImgMaxWords = 11776;  // 46 KiB of LDS for the network image
 constexpr uint32_t kStageWords = 4096;    // 16 KiB of LDS for staged successors
 
 // ------------------------------------------------------------------ kernel
-struct ExploreArgs {
-  TableDev t;
-  const uint32_t* img;
-  uint32_t img_words;
-  uint32_t img_stride;  // img_words rounded up to 4
-  const uint32_t* frontier_in;
-  uint64_t n_in;
-  uint32_t* frontier_out;
-  uint64_t cap_out;
-  uint32_t* dead;
-  uint64_t dead_cap;
-  uint64_t* ctr;  // [0] next-frontier tail [1] deadlocks [2] transitions [3] flags [4] local duplicates
-  uint32_t dedup; // nonzero: drop duplicates within each staged chunk before probing
-};
 
 enum : uint32_t { kFlagFrontierOverflow = 1, kFlagTableFull = 2 };
 
@@ -146,6 +132,83 @@ __device__ __forceinline__ void emit_successors(const uint32_t* img, const uint3
   }
 }
 
+template <int S>
+__device__ __forceinline__ void load_slot(const uint32_t* p, uint32_t (&k)[S]) {
+  if constexpr (S == 4) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    k[0] = v.x;
+    k[1] = v.y;
+    k[2] = v.z;
+    k[3] = v.w;
+  } else if constexpr (S == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    k[0] = v.x;
+    k[1] = v.y;
+  } else {
+    k[0] = *p;
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) {
+  if constexpr (S == 4) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(k[0], k[1], k[2], k[3]);
+  } else if constexpr (S == 2) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(k[0], k[1]);
+  } else {
+    *p = k[0];
+  }
+}
+
+// Write every successor of this state, in the order emit_successors numbers
+// them, to out[k * S] (global memory; one lane writes a contiguous run).
+template <int S>
+__device__ __forceinline__ void emit_all(const uint32_t* img, const uint32_t (&sw)[S],
+                                         uint32_t* out) {
+  const uint32_t P = img[0], R = img[1];
+  uint32_t* o = out;
+  for (uint32_t p = 0; p < P; ++p) {
+    const uint32_t f = img[4 + p];
+    const uint32_t l = get_field<S>(sw, f);
+    const uint32_t ob = img[4 + P + p];
+    const uint32_t s0 = img[ob + l], s1 = img[ob + l + 1];
+    for (uint32_t t = s0; t < s1; ++t) {
+      uint32_t succ[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) succ[x] = sw[x];
+      set_field<S>(succ, f, img[t]);
+      store_slot<S>(o, succ);
+      o += S;
+    }
+  }
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t rb = img[4 + 2 * P + r];
+    const uint32_t np = img[rb];
+    uint32_t prod = 1;
+    for (uint32_t i = 0; i < np && prod; ++i) {
+      const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
+      const uint32_t l = get_field<S>(sw, img[4 + q]);
+      prod *= img[ob + l + 1] - img[ob + l];
+    }
+    for (uint32_t c = 0; c < prod; ++c) {
+      uint32_t succ[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) succ[x] = sw[x];
+      uint32_t rem = c;
+      for (uint32_t i = 0; i < np; ++i) {
+        const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
+        const uint32_t fq = img[4 + q];
+        const uint32_t l = get_field<S>(sw, fq);
+        const uint32_t b0 = img[ob + l], cnt = img[ob + l + 1] - b0;
+        set_field<S>(succ, fq, img[b0 + rem % cnt]);
+        rem /= cnt;
+      }
+      store_slot<S>(o, succ);
+      o += S;
+    }
+  }
+}
+
 // Exclusive prefix sum over the 64 lanes of a wavefront; *total receives the
 // wavefront's sum.
 __device__ inline uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
@@ -197,6 +260,49 @@ __device__ __forceinline__ uint32_t dedup_hash(const uint32_t (&k)[S]) {
   return h ^ (h >> 15);
 }
 
+// Local duplicate filter (the block-local state cache of the tool, Sec. 3):
+// the first occurrence of a successor among the n_st staged in this chunk
+// claims an entry of the wavefront's LDS set `dtab`; later occurrences find it
+// and are marked in *dupmask (bit r: this lane's staged index of round r,
+// r0 = 64 r).  Returns the wavefront's number of marked successors.  Must be
+// reached by the whole wavefront; the staged chunk is only read.
+template <int S>
+__device__ inline uint32_t dedup_chunk(uint32_t* dtab, const uint32_t* stage, uint32_t n_st,
+                                       uint32_t* dupmask) {
+  constexpr uint32_t D = dedup_entries<S>();
+  const int lane = __lane_id();
+  for (uint32_t e = lane; e < D; e += 64) dtab[e] = kEmpty;
+  wave_lds_sync();
+  uint32_t dups = 0, mask = 0;
+  for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
+    const uint32_t idx = r0 + lane;
+    if (idx < n_st) {
+      uint32_t key[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) key[x] = stage[idx * S + x];
+      uint32_t h = dedup_hash<S>(key) & (D - 1);
+      while (true) {
+        uint32_t prev = kEmpty;
+        if (__hip_atomic_compare_exchange_strong(&dtab[h], &prev, idx, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT))
+          break;  // first occurrence
+        bool same = true;
+#pragma unroll
+        for (int x = 0; x < S; ++x) same &= stage[prev * S + x] == key[x];
+        if (same) {
+          mask |= 1u << r;
+          ++dups;
+          break;
+        }
+        h = (h + 1) & (D - 1);
+      }
+    }
+  }
+  wave_lds_sync();
+  *dupmask = mask;
+  return wave_sum(dups);
+}
+
 // A wavefront owns 64 frontier states and its own slice of the LDS staging
 // buffer, and runs generate -> find-or-put -> append on its own; no barrier
 // couples it to the other wavefronts of its workgroup, so successor
@@ -234,45 +340,10 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
                          static_cast<int>(hi) - static_cast<int>(off), stage);
     wave_lds_sync();
     const uint32_t n_st = hi - lo;
-    // Local duplicate filter (the block-local state cache of the tool): the
-    // first occurrence of a successor in this chunk claims an entry of the
-    // wavefront's LDS set; later occurrences find it and skip the table
-    // probe (their result would be SEEN).  dupmask bit r: this lane's key of
-    // round r is such a later occurrence.
     uint32_t dupmask = 0;
     if (j.dtab) {
-      constexpr uint32_t D = dedup_entries<S>();
-      for (uint32_t e = lane; e < D; e += 64) j.dtab[e] = kEmpty;
-      wave_lds_sync();
-      uint32_t dups = 0;
-      for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
-        const uint32_t idx = r0 + lane;
-        if (idx < n_st) {
-          uint32_t key[S];
-#pragma unroll
-          for (int x = 0; x < S; ++x) key[x] = stage[idx * S + x];
-          uint32_t h = dedup_hash<S>(key) & (D - 1);
-          while (true) {
-            uint32_t prev = kEmpty;
-            if (__hip_atomic_compare_exchange_strong(&j.dtab[h], &prev, idx, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_WAVEFRONT))
-              break;  // first occurrence
-            bool same = true;
-#pragma unroll
-            for (int x = 0; x < S; ++x) same &= stage[prev * S + x] == key[x];
-            if (same) {
-              dupmask |= 1u << r;
-              ++dups;
-              break;
-            }
-            h = (h + 1) & (D - 1);
-          }
-        }
-      }
-      const uint32_t wd = wave_sum(dups);
+      const uint32_t wd = dedup_chunk<S>(j.dtab, stage, n_st, &dupmask);
       if (lane == 0 && wd) atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[4]), wd);
-      wave_lds_sync();
     }
     for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
       const uint32_t idx = r0 + lane;
@@ -306,79 +377,258 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
   }
 }
 
-// One BFS level of one exploration: 256 frontier states per workgroup.
-template <int S, int B, int G, int U>
-__global__ __launch_bounds__(256) void explore_level_kernel(ExploreArgs a) {
+// ------------------------------------------------- two-kernel BFS level
+// A level (or a slice of it) of a single exploration runs as two kernels:
+//   gen_level_kernel<S>: every wavefront expands 64 frontier states from the
+//     LDS network image (counts, deadlocks, transitions) and writes their
+//     successors to a successor buffer: each lane its own contiguous run, or,
+//     with the duplicate filter, chunk by chunk through LDS staging without
+//     in-chunk duplicates;
+//   append_kernel<S,B,G,U>: find-or-put of that buffer (one key per lane,
+//     grid-stride, as the isolated find-or-put) that appends the NEW keys to
+//     the next frontier.
+// Splitting keeps the table probes in a kernel with the register budget and
+// occupancy of the isolated find-or-put instead of sharing waves with the
+// successor generation.
+
+struct GenArgs {
+  const uint32_t* img;
+  uint32_t img_words;
+  uint32_t img_stride;  // img_words rounded up to 4
+  const uint32_t* frontier_in;
+  uint64_t n_in;
+  uint32_t* succ;       // successor keys, S words each
+  uint64_t succ_cap;    // keys
+  uint32_t* dead;
+  uint64_t dead_cap;
+  uint64_t* ctr;  // [1] deadlocks [2] transitions [3] flags [4] local duplicates [5] successors written
+  uint32_t dedup;
+};
+
+// 64 frontier states [first, first + 64) of the slice: successors to a.succ.
+template <int S>
+__device__ inline void gen_wave(const GenArgs& a, const uint32_t* img, uint32_t* stage,
+                                uint32_t* dtab, uint64_t first) {
+  constexpr uint32_t CAP = kStageWords / 4 / S;  // staged successors per chunk
+  const int lane = __lane_id();
+  const uint64_t i = first + lane;
+  const bool has = i < a.n_in;
+  uint32_t sw[S];
+#pragma unroll
+  for (int x = 0; x < S; ++x) sw[x] = 0;
+  if (has) load_slot<S>(a.frontier_in + i * S, sw);
+  const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
+  if (has && c == 0) {
+    const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[1]), 1ull);
+    if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
+  }
+  uint32_t total = 0;
+  const uint32_t off = wave_exclusive_scan(c, &total);
+  if (lane == 0 && total)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[2]), static_cast<unsigned long long>(total));
+  if (!dtab) {
+    // no filter: every lane writes its own successors straight to their
+    // place in the buffer, one pass over its transitions
+    unsigned long long base = 0;
+    if (lane == 0 && total)
+      base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[5]),
+                       static_cast<unsigned long long>(total));
+    base = __shfl(base, 0, 64);
+    if (base + total > a.succ_cap) {
+      if (lane == 0)  // cannot happen with the host's bound; refuse rather than overrun
+        atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
+    } else if (c) {
+      emit_all<S>(img, sw, a.succ + (base + off) * S);
+    }
+    return;
+  }
+  for (uint32_t lo = 0; lo < total; lo += CAP) {
+    const uint32_t hi = min(total, lo + CAP);
+    if (c && off < hi && off + c > lo)
+      emit_successors<S>(img, sw, static_cast<int>(lo) - static_cast<int>(off),
+                         static_cast<int>(hi) - static_cast<int>(off), stage);
+    wave_lds_sync();
+    const uint32_t n_st = hi - lo;
+    uint32_t dupmask = 0;
+    const uint32_t wd = dedup_chunk<S>(dtab, stage, n_st, &dupmask);
+    if (lane == 0 && wd) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[4]), wd);
+    const uint32_t n_keep = n_st - wd;
+    unsigned long long base = 0;
+    if (lane == 0 && n_keep)
+      base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[5]),
+                       static_cast<unsigned long long>(n_keep));
+    base = __shfl(base, 0, 64);
+    if (base + n_keep > a.succ_cap) {
+      // cannot happen with the host's bound; refuse rather than overrun
+      if (lane == 0)
+        atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
+    } else {
+      uint32_t kept = 0;  // kept successors of earlier rounds
+      for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
+        const uint32_t idx = r0 + lane;
+        const bool keep = idx < n_st && !((dupmask >> r) & 1u);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+          uint32_t key[S];
+          load_slot<S>(stage + idx * S, key);
+          const uint64_t pos = base + kept + __popcll(m & ((1ull << lane) - 1ull));
+          store_slot<S>(a.succ + pos * S, key);
+        }
+        kept += static_cast<uint32_t>(__popcll(m));
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   extern __shared__ uint32_t smem[];
   uint32_t* img = smem;
+  // staging and filter space only with the duplicate filter
   uint32_t* stage = smem + a.img_stride + (threadIdx.x >> 6) * (kStageWords / 4);
-  for (uint32_t i = threadIdx.x; i < a.img_words; i += 256) img[i] = a.img[i];
+  uint32_t* dtab = a.dedup ? smem + a.img_stride + kStageWords +
+                                 (threadIdx.x >> 6) * dedup_entries<S>()
+                           : nullptr;
+  for (uint32_t k = threadIdx.x; k < a.img_words; k += 256) img[k] = a.img[k];
   __syncthreads();
-  WaveJob j;
-  j.t = a.t;
-  j.img = img;
-  j.frontier_in = a.frontier_in;
-  j.first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
-  j.n_in = a.n_in;
-  j.frontier_out = a.frontier_out;
-  j.cap_out = a.cap_out;
-  j.dead = a.dead;
-  j.dead_tag = nullptr;
-  j.tag = 0;
-  j.dead_cap = a.dead_cap;
-  j.dead_ctr = &a.ctr[1];
-  j.ctr = a.ctr;
-  j.dtab = a.dedup ? smem + a.img_stride + kStageWords + (threadIdx.x >> 6) * dedup_entries<S>()
-                   : nullptr;
+  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
+  if (first < a.n_in) gen_wave<S>(a, img, stage, dtab, first);
+}
+
+struct AppendArgs {
+  TableDev t;
+  const uint32_t* keys;    // S words per key
+  uint64_t keys_cap;       // keys the buffer holds
+  const uint64_t* n_keys;  // device memory: the number of keys (clamped to keys_cap)
+  uint32_t* frontier_out;
+  uint64_t cap_out;        // states
+  uint64_t* ctr;           // [0] next-frontier tail [3] flags
+};
+
+constexpr uint32_t kAppendKeys = 256;  // NEW keys a wavefront gathers in LDS
+
+// Move a wavefront's cnt gathered NEW keys from LDS to the next frontier:
+// one atomic add reserves the room, the copy is coalesced.
+template <int S>
+__device__ inline void append_flush(const AppendArgs& a, const uint32_t* buf, uint32_t cnt) {
+  if (cnt == 0) return;
+  const int lane = __lane_id();
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[0]),
+                                  static_cast<unsigned long long>(cnt));
+  base = __shfl(base, 0, 64);
+  if (lane == 0 && base + cnt > a.cap_out)
+    atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
+  for (uint32_t k = lane; k < cnt; k += 64) {
+    if (base + k < a.cap_out) {
+      uint32_t key[S];
+      load_slot<S>(buf + k * S, key);
+      store_slot<S>(a.frontier_out + (base + k) * S, key);
+    }
+  }
+}
+
+template <int S, int B, int G, int U>
+__global__ __launch_bounds__(256) void append_kernel(AppendArgs a) {
+  __shared__ __align__(16) uint32_t sbuf[4][kAppendKeys * S];
+  uint32_t* buf = sbuf[threadIdx.x >> 6];
+  const int lane = __lane_id();
+  // a generation that overran the buffer has flagged it; never read past it
+  const uint64_t n = min(*a.n_keys, a.keys_cap);
+  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
   LaneStats st;
-  if (j.first < j.n_in) expand_wave<S, B, G, U>(j, stage, st);
+  uint32_t cnt = 0;  // gathered NEW keys (wavefront-uniform)
+  bool full = false;
+  for (uint64_t base = wave * 64; base < n; base += n_waves * 64) {
+    const uint64_t idx = base + lane;
+    const bool act = idx < n;
+    uint32_t key[S];
+#pragma unroll
+    for (int x = 0; x < S; ++x) key[x] = 0;
+    if (act) load_slot<S>(a.keys + idx * S, key);
+    const uint8_t r = find_or_put_lanes<S, B, G, U>(a.t, key, act, st);
+    const bool is_new = act && r == kNew;
+    full |= act && r == kFull;
+    const uint64_t m = __ballot(is_new);
+    if (is_new) store_slot<S>(buf + (cnt + __popcll(m & ((1ull << lane) - 1ull))) * S, key);
+    cnt += static_cast<uint32_t>(__popcll(m));
+    if (cnt > kAppendKeys - 64) {
+      wave_lds_sync();
+      append_flush<S>(a, buf, cnt);
+      wave_lds_sync();
+      cnt = 0;
+    }
+  }
+  wave_lds_sync();
+  append_flush<S>(a, buf, cnt);
+  if (__ballot(full) && lane == 0)
+    atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagTableFull);
   flush_stats(a.t, st, nullptr);
 }
 
 template <int S, int B, int G, int U>
-hipError_t launch_level(const ExploreArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
+hipError_t launch_append(const AppendArgs& a, uint32_t cus, hipStream_t s) {
+  // as many workgroups as can be resident at once (grid-stride over rounds)
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, append_kernel<S, B, G, U>, 256, 0) !=
+            hipSuccess ||
+        b <= 0)
+      b = 2;
+    per_cu = b;
+  }
+  hipLaunchKernelGGL((append_kernel<S, B, G, U>), dim3(cus * static_cast<uint32_t>(per_cu)),
+                     dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_gen(const GenArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
   if (lds > 65536) {  // more than the default per-workgroup LDS: ask for it
-    const hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&explore_level_kernel<S, B, G, U>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gen_level_kernel<S>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((explore_level_kernel<S, B, G, U>), dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((gen_level_kernel<S>), dim3(grid), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
 template <int S, int B, int G>
-hipError_t level_u(uint32_t U, const ExploreArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
+hipError_t append_u(uint32_t U, const AppendArgs& a, uint32_t cus, hipStream_t s) {
   switch (U) {
-    case 1: return launch_level<S, B, G, 1>(a, grid, lds, s);
-    case 2: return launch_level<S, B, G, 2>(a, grid, lds, s);
-    case 4: return launch_level<S, B, G, 4>(a, grid, lds, s);
-    case 8: return launch_level<S, B, G, 8>(a, grid, lds, s);
+    case 1: return launch_append<S, B, G, 1>(a, cus, s);
+    case 2: return launch_append<S, B, G, 2>(a, cus, s);
+    case 4: return launch_append<S, B, G, 4>(a, cus, s);
+    case 8: return launch_append<S, B, G, 8>(a, cus, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int S, int B>
-hipError_t level_g(uint32_t G, uint32_t U, const ExploreArgs& a, uint32_t grid, size_t lds,
-                   hipStream_t s) {
+hipError_t append_g(uint32_t G, uint32_t U, const AppendArgs& a, uint32_t cus, hipStream_t s) {
   switch (G) {
-    case 8: return level_u<S, B, 8>(U, a, grid, lds, s);
-    case 16: return level_u<S, B, 16>(U, a, grid, lds, s);
-    case 32: return level_u<S, B, 32>(U, a, grid, lds, s);
-    case 64: return level_u<S, B, 64>(U, a, grid, lds, s);
+    case 8: return append_u<S, B, 8>(U, a, cus, s);
+    case 16: return append_u<S, B, 16>(U, a, cus, s);
+    case 32: return append_u<S, B, 32>(U, a, cus, s);
+    case 64: return append_u<S, B, 64>(U, a, cus, s);
   }
   return hipErrorInvalidValue;
 }
 
+// Find-or-put-and-append dispatch over (B, G, U) for slot width S.
 template <int S>
-hipError_t level_b(uint32_t B, uint32_t G, uint32_t U, const ExploreArgs& a, uint32_t grid,
-                   size_t lds, hipStream_t s) {
+hipError_t append_b(uint32_t B, uint32_t G, uint32_t U, const AppendArgs& a, uint32_t cus,
+                    hipStream_t s) {
   switch (B) {
-    case 4: return level_g<S, 4>(G, U, a, grid, lds, s);
-    case 8: return level_g<S, 8>(G, U, a, grid, lds, s);
-    case 16: return level_g<S, 16>(G, U, a, grid, lds, s);
-    case 32: return level_g<S, 32>(G, U, a, grid, lds, s);
-    case 64: return level_g<S, 64>(G, U, a, grid, lds, s);
+    case 4: return append_g<S, 4>(G, U, a, cus, s);
+    case 8: return append_g<S, 8>(G, U, a, cus, s);
+    case 16: return append_g<S, 16>(G, U, a, cus, s);
+    case 32: return append_g<S, 32>(G, U, a, cus, s);
+    case 64: return append_g<S, 64>(G, U, a, cus, s);
   }
   return hipErrorInvalidValue;
 }

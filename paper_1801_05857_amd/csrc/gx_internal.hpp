@@ -17,6 +17,8 @@ struct gx_explore_buffers {
   uint64_t f_cap[2] = {0, 0};  // states
   uint32_t* dead = nullptr;
   uint64_t dead_cap = 0;  // states
+  uint32_t* succ = nullptr;  // successors of a level slice, before the table probe
+  uint64_t succ_cap = 0;     // states
   uint64_t* ctr = nullptr;  // 8 counters
   uint8_t* status = nullptr;
   uint32_t* key = nullptr;  // 4 words

@@ -115,7 +115,7 @@ void free_table(gx_table* t) {
   if (t->counters) (void)hipFree(t->counters);
   gx_explore_buffers& e = t->eb;
   for (void* p : {static_cast<void*>(e.img), static_cast<void*>(e.f[0]),
-                  static_cast<void*>(e.f[1]), static_cast<void*>(e.dead),
+                  static_cast<void*>(e.f[1]), static_cast<void*>(e.dead), static_cast<void*>(e.succ),
                   static_cast<void*>(e.ctr), static_cast<void*>(e.status),
                   static_cast<void*>(e.key)})
     if (p) (void)hipFree(p);
