@@ -170,29 +170,50 @@ def cpu_baseline(target_s: float = 15.0):
                       f"(2^{k} distinct, each twice, shuffled), one thread, {dt:.1f} s"}
 
 
-def run_explore_leg(gx, torch, W, spec="1:12:64:6:3:0.17"):
-    """States explored per second on one large random network (12 processes
-    of 64 declared states, 6 live, out-degree 3: 3-word vectors), with the
-    table's buffers resident (a first exploration sizes them)."""
-    seed, P, ns, live, deg, sink = spec.split(":")
-    net = W.random_lts(int(seed), int(P), int(ns), int(live), int(deg), 32, 0.25, float(sink))
+def explore_bytes_per_state(f: float, B: int, S: int) -> float:
+    """Algorithmic HBM bytes per explored state of the two-kernel level: f
+    successors each probe one bucket (at least a 64-byte granule) and pass
+    through the successor buffer (written and read, 4S bytes each way); the
+    state is read from the frontier and written to the next one (4S each);
+    its claim writes back one granule."""
+    return f * (max(4 * B, GRANULE) + 2 * 4 * S) + 2 * 4 * S + GRANULE
+
+
+def run_explore_leg(gx, torch, W, live=8, B=32, G=8, U=1, slots=None):
+    """States explored per second on the large plain-path workload (12
+    processes of 64 declared states, 3-word vectors, 3.3e9 reachable states,
+    192 GB table), with the table's buffers resident (a first exploration
+    sizes them), timed on the second exploration into the cleared table."""
+    net = W.large_random_network(live)
     w = gx.network_words(net)
-    t = gx.Table(w, 32, 1 << 30, subgroup=8, keys_per_subgroup=2, max_hashes=16)
+    slots = slots or W.LARGE_TABLE_SLOTS
+    torch.cuda.empty_cache()
+    t = gx.Table(w, B, slots, subgroup=G, keys_per_subgroup=U, max_hashes=16)
+    t0 = time.perf_counter()
     gx.explore(net, t)
+    cold = time.perf_counter() - t0
     t.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = gx.explore(net, t)
     dt = time.perf_counter() - t0
-    per_state = r.n_transitions / r.n_states
-    S = t.info.slot_words
-    bps = per_state * max(4 * 32, GRANULE) + 8 * S + GRANULE
+    st = t.stats()
+    info = t.info
+    f = r.n_transitions / r.n_states
+    bps = explore_bytes_per_state(f, B, info.slot_words)
     t.close()
-    return {"workload": f"random network {spec} (seed:procs:states:live:degree:sink), "
-                        f"{w}-word vectors, buckets of 32 words, subgroup 8",
+    return {"workload": (f"random network: 12 processes x 64 declared states ({live} live), "
+                         f"out-degree 3, 32 labels, 25% rendezvous, seed 1, sink 0.15; "
+                         f"{w}-word vectors; table {info.n_slots} slots ({info.bytes / 1e9:.0f} GB), "
+                         f"buckets of {B} words, subgroup {G}, {U} key(s) in flight"),
             "states": r.n_states, "transitions": r.n_transitions, "levels": len(r.levels),
-            "seconds": round(dt, 4), "states_per_s": round(r.n_states / dt),
-            "successors_per_state": round(per_state, 2),
+            "seconds": round(dt, 4), "cold_seconds": round(cold, 4),
+            "states_per_s": round(r.n_states / dt),
+            "lookups_per_s": round(r.n_transitions / dt),
+            "successors_per_state": round(f, 2),
+            "probes_per_lookup": round(st.probes / max(1, st.lookups), 4),
+            "load_factor": round(r.n_states / info.n_slots, 3),
+            "algorithmic_bytes_per_state": round(bps, 1),
             "algorithmic_GBps": round(r.n_states * bps / dt / 1e9, 1),
             "roofline_frac": round(r.n_states * bps / dt / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -460,7 +481,7 @@ def main():
                 s = t.stats()
                 per_state = (r.n_transitions / max(1, r.n_states))
                 S = t.info.slot_words
-                bps = per_state * max(4 * args.bucket, GRANULE) + 8 * S + GRANULE
+                bps = explore_bytes_per_state(per_state, args.bucket, S)
                 print(json.dumps({"net": spec, "words": w, "states": r.n_states,
                                   "transitions": r.n_transitions, "levels": len(r.levels),
                                   "max_level": int(r.levels.max()), "deadlocks": len(r.deadlocks),

@@ -85,7 +85,7 @@ def _load():
         lib.oracle_pack.argtypes = [u32, vp, vp, u64, vp]
         net_args = [u32, vp, vp, vp, vp, vp, vp, u32, u32, vp]
         lib.oracle_explore.restype = i32
-        lib.oracle_explore.argtypes = net_args + [u64, i32, ctypes.POINTER(_Result)]
+        lib.oracle_explore.argtypes = net_args + [u64, u32, i32, ctypes.POINTER(_Result)]
         lib.oracle_bruteforce.restype = i32
         lib.oracle_bruteforce.argtypes = net_args + [i32, ctypes.POINTER(_Result)]
         lib.oracle_result_free.argtypes = [ctypes.POINTER(_Result)]
@@ -181,11 +181,14 @@ def _collect(res: _Result, want_visited: bool) -> OracleResult:
     return out
 
 
-def explore(net, max_states: int = 0, want_visited: bool = False) -> OracleResult:
-    """Plain BFS of the synchronous product (Sec. 3)."""
+def explore(net, max_states: int = 0, want_visited: bool = False,
+            max_levels: int = 0) -> OracleResult:
+    """Plain BFS of the synchronous product (Sec. 3).  max_levels > 0: stop
+    once levels 0 .. max_levels-1 are known (a BFS prefix)."""
     args, keep = _flatten(net)
     res = _Result()
-    rc = _load().oracle_explore(*args, max_states, int(want_visited), ctypes.byref(res))
+    rc = _load().oracle_explore(*args, max_states, max_levels, int(want_visited),
+                                ctypes.byref(res))
     del keep
     if rc == -1:
         raise ValueError("invalid network")

@@ -352,11 +352,15 @@ static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
 
 // Plain breadth-first search over std::unordered_set.
 // Returns 0 on success, -1 on an invalid network, -2 when more than
-// max_states states are reachable (max_states == 0: no limit).
+// max_states states are reachable (max_states == 0: no limit).  With
+// max_levels > 0 the search stops once levels 0 .. max_levels-1 are known
+// (a BFS prefix: level counts of those levels, the states at distance below
+// max_levels, and transitions and deadlocks of the levels expanded so far).
 int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
                    const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
                    const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
-                   uint64_t max_states, int want_visited, oracle_result* out) {
+                   uint64_t max_states, uint32_t max_levels, int want_visited,
+                   oracle_result* out) {
   Net net;
   Plan plan;
   if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
@@ -375,6 +379,7 @@ int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial
   frontier.push_back(init);
   levels.push_back(1);
   while (!frontier.empty()) {
+    if (max_levels && levels.size() >= max_levels) break;
     next.clear();
     for (const Vec& s : frontier) {
       successors(net, unpack(plan, s), &succ);

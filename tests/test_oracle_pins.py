@@ -270,3 +270,18 @@ def test_successor_counts_sum_to_transitions():
         # closure: every successor is in the reachable set
         vis = {tuple(v) for v in r.visited.tolist()}
         assert all(tuple(v) in vis for v in succ.tolist())
+
+
+def test_bfs_prefix_matches_full_search():
+    """explore(max_levels=k) gives the first k level counts of the full BFS
+    and stops before expanding level k-1 (fewer transitions counted), unless
+    the search ends first."""
+    for net in [W.token_ring(7), W.tiny_cycles(), W.large_random_network(live=3)]:
+        full = oracle.explore(net)
+        for k in (1, 2, 5, len(full.levels), len(full.levels) + 3):
+            pre = oracle.explore(net, max_levels=k)
+            assert pre.levels.tolist() == full.levels[:k].tolist()
+            if k <= len(full.levels):  # the last known level is not expanded
+                assert pre.n_transitions < full.n_transitions
+            else:
+                assert pre.n_transitions == full.n_transitions

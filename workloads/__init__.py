@@ -181,6 +181,22 @@ def random_lts(seed: int, n_procs: int, n_states, live, out_degree: int = 3,
                 name or f"random_s{seed}_p{n_procs}", seed=seed, live=lv.tolist())
 
 
+def large_random_network(live: int = 8) -> Network:
+    """The large plain-path workload: 12 processes of 64 declared local states
+    (6-bit fields, so 3-word vectors), out-degree 3 with uniform targets, a
+    32-label alphabet of which 25% are 2-party rendezvous between seeded
+    process pairs, seed 1, sink probability 0.15.  With 8 live states per
+    process 3,304,390,656 states are reachable (38 BFS levels, 90.5 G
+    transitions, no deadlocks); ``live`` smaller gives the same family at
+    sizes the oracle enumerates (live 3: a few hundred thousand states)."""
+    return random_lts(1, 12, 64, live, 3, 32, 0.25, 0.15, name=f"large_random_l{live}")
+
+
+# Table slots for the large workload: 12e9 slots of 16 bytes (192 GB), load
+# factor 0.28 at its 3.3e9 states.
+LARGE_TABLE_SLOTS = 12_000_000_000
+
+
 # ------------------------------------------------------------- key streams
 MASK62 = (1 << 62) - 1
 
