@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--batch", action="store_true",
                     help="batched exploration of --batch-n uneven random networks")
     ap.add_argument("--batch-n", type=int, default=1024)
+    ap.add_argument("--batch-bucket", type=int, default=0, help="0: autotuned per instance")
+    ap.add_argument("--batch-subgroup", type=int, default=0, help="0: autotuned per instance")
+    ap.add_argument("--batch-kps", type=int, default=0, help="0: autotuned per instance")
     ap.add_argument("--serve", action="store_true",
                     help="served exploration: Poisson request streams at several rates")
     ap.add_argument("--serve-n", type=int, default=120, help="requests per rate")
@@ -273,14 +276,15 @@ def run_token_ring(gx, torch, W, sizes=range(2, 17)):
     return rows
 
 
-def run_batch(gx, torch, W, n, seed=11, hashes=16):
+def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
     """Batched exploration of n uneven random networks: one persistent launch
     per kernel class replayed from a hipGraph, against one gx_explore call per
     instance on pre-created tables (both clear their tables and start over)."""
     nets, bounds = W.batch_networks(n, seed)
     caps = [2 * c for c in bounds]  # table slots: load factor at most 0.5
     t_setup = time.perf_counter()
-    b = gx.Batch(nets, caps, use_graph=True, max_hashes=hashes)
+    b = gx.Batch(nets, caps, use_graph=True, max_hashes=hashes, bucket_words=B, subgroup=G,
+                 keys_per_subgroup=U)
     setup_s = time.perf_counter() - t_setup
     b.run()
     torch.cuda.synchronize()
@@ -451,7 +455,8 @@ def main():
             print(json.dumps(row), flush=True)
         return
     if args.batch:
-        print(json.dumps(run_batch(gx, torch, W, args.batch_n)), flush=True)
+        print(json.dumps(run_batch(gx, torch, W, args.batch_n, B=args.batch_bucket,
+                                   G=args.batch_subgroup, U=args.batch_kps)), flush=True)
         return
     if args.serve:
         for row in run_serve(gx, torch, W, args.serve_n):

@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
     __syncthreads();
     if (sh_stop) break;
     __threadfence();  // acquire: the level's frontier and instance state
-    const uint32_t iid = sh_inst;
-    const uint32_t tile = sh_tile;
+    const uint32_t iid = uniform32(sh_inst);
+    const uint32_t tile = uniform32(sh_tile);
     const BatchInst& in = a.inst[iid];
     BatchState& bs = a.state[iid];
     if (iid != cached) {
@@ -181,13 +181,14 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
     }
     __syncthreads();
     WaveJob j;
-    j.t = in.t;
+    j.t = uniform_table(in.t);
     j.img = img;
-    j.frontier_in = in.f[bs.cur];
+    const uint32_t cur = uniform32(bs.cur);
+    j.frontier_in = uniform_ptr(static_cast<const uint32_t*>(in.f[cur]));
     j.first = static_cast<uint64_t>(tile) * 256 + (threadIdx.x & ~63u);
-    j.n_in = bs.n_in;
-    j.frontier_out = in.f[bs.cur ^ 1];
-    j.cap_out = in.cap;
+    j.n_in = uniform64(bs.n_in);
+    j.frontier_out = uniform_ptr(in.f[cur ^ 1]);
+    j.cap_out = uniform64(in.cap);
     j.dead = a.dead;
     j.dead_tag = a.dead_tag;
     j.tag = iid;

@@ -106,6 +106,33 @@ struct TableDev {
   uint64_t* counters;  // kNumCounters
 };
 
+// A value every lane of the wavefront holds the same copy of, moved to a
+// scalar register (for table descriptors read from memory at run time, so
+// they do not take vector registers in the probe loops).
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return (static_cast<uint64_t>(uniform32(static_cast<uint32_t>(x >> 32))) << 32) |
+         uniform32(static_cast<uint32_t>(x));
+}
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform64(reinterpret_cast<uint64_t>(p)));
+}
+__device__ __forceinline__ TableDev uniform_table(const TableDev& t) {
+  TableDev u;
+  u.words = uniform_ptr(t.words);
+  u.n_buckets = uniform64(t.n_buckets);
+  u.hc = uniform_ptr(t.hc);
+  u.seed = uniform64(t.seed);
+  u.a0 = uniform64(t.a0);
+  u.c0 = uniform64(t.c0);
+  u.H = uniform32(t.H);
+  u.counters = uniform_ptr(t.counters);
+  return u;
+}
+
 template <int S, int B, int G>
 struct Geo {
   static_assert(S == 1 || S == 2 || S == 4, "slot words");

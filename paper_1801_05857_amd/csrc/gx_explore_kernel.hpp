@@ -315,29 +315,45 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
   const int lane = __lane_id();
   const uint64_t i = j.first + lane;
   const bool has = i < j.n_in;
-  uint32_t sw[S];
-#pragma unroll
-  for (int x = 0; x < S; ++x) sw[x] = has ? j.frontier_in[i * S + x] : 0u;
-  const uint32_t c = has ? count_successors<S>(j.img, sw) : 0u;
-  if (has && c == 0) {
-    const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(j.dead_ctr), 1ull);
-    if (j.dead_ctr != &j.ctr[1]) atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[1]), 1ull);
-    if (d < j.dead_cap) {
-#pragma unroll
-      for (int x = 0; x < S; ++x) j.dead[d * S + x] = sw[x];
-      if (j.dead_tag) j.dead_tag[d] = j.tag;
-    }
-  }
   uint32_t total = 0;
-  const uint32_t off = wave_exclusive_scan(c, &total);
-  if (lane == 0 && total)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[2]), static_cast<unsigned long long>(total));
+  {
+    uint32_t sw[S];
+#pragma unroll
+    for (int x = 0; x < S; ++x) sw[x] = has ? j.frontier_in[i * S + x] : 0u;
+    const uint32_t c = has ? count_successors<S>(j.img, sw) : 0u;
+    if (has && c == 0) {
+      const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(j.dead_ctr), 1ull);
+      if (j.dead_ctr != &j.ctr[1])
+        atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[1]), 1ull);
+      if (d < j.dead_cap) {
+#pragma unroll
+        for (int x = 0; x < S; ++x) j.dead[d * S + x] = sw[x];
+        if (j.dead_tag) j.dead_tag[d] = j.tag;
+      }
+    }
+    (void)wave_exclusive_scan(c, &total);
+    if (lane == 0 && total)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[2]),
+                static_cast<unsigned long long>(total));
+  }
 
   for (uint32_t lo = 0; lo < total; lo += CAP) {
     const uint32_t hi = min(total, lo + CAP);
-    if (c && off < hi && off + c > lo)
-      emit_successors<S>(j.img, sw, static_cast<int>(lo) - static_cast<int>(off),
-                         static_cast<int>(hi) - static_cast<int>(off), stage);
+    {
+      // The state, its successor count and offset are recomputed for every
+      // chunk rather than kept: nothing of the generation stays live in
+      // registers while the chunk is probed, which keeps the probe phase at
+      // the find-or-put kernel's register budget.
+      uint32_t sw[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) sw[x] = has ? j.frontier_in[i * S + x] : 0u;
+      const uint32_t c = has ? count_successors<S>(j.img, sw) : 0u;
+      uint32_t t2 = 0;
+      const uint32_t off = wave_exclusive_scan(c, &t2);
+      if (c && off < hi && off + c > lo)
+        emit_successors<S>(j.img, sw, static_cast<int>(lo) - static_cast<int>(off),
+                           static_cast<int>(hi) - static_cast<int>(off), stage);
+    }
     wave_lds_sync();
     const uint32_t n_st = hi - lo;
     uint32_t dupmask = 0;
@@ -345,6 +361,11 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
       const uint32_t wd = dedup_chunk<S>(j.dtab, stage, n_st, &dupmask);
       if (lane == 0 && wd) atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[4]), wd);
     }
+    // NEW keys are compacted in place to the front of the staging area (a
+    // round writes below the end of the keys it has read), then moved to the
+    // next frontier with one atomic add and coalesced stores per chunk.
+    uint32_t n_new = 0;
+    bool full = false;
     for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
       const uint32_t idx = r0 + lane;
       const bool act = idx < n_st && !((dupmask >> r) & 1u);
@@ -353,25 +374,29 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
       for (int x = 0; x < S; ++x) key[x] = act ? stage[idx * S + x] : 0u;
       const uint8_t res = find_or_put_lanes<S, B, G, U>(j.t, key, act, st);
       const bool is_new = act && res == kNew;
+      full |= act && res == kFull;
       const uint64_t m = __ballot(is_new);
-      if (m) {
-        unsigned long long base = 0;
-        if (lane == 0)
-          base = atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[0]),
-                           static_cast<unsigned long long>(__popcll(m)));
-        base = __shfl(base, 0, 64);
-        if (is_new) {
-          const uint64_t pos = base + __popcll(m & ((1ull << lane) - 1ull));
-          if (pos < j.cap_out) {
+      wave_lds_sync();  // every lane's key of this round is read before any write
+      if (is_new) {
+        const uint32_t pos = n_new + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
 #pragma unroll
-            for (int x = 0; x < S; ++x) j.frontier_out[pos * S + x] = key[x];
-          } else {
-            atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagFrontierOverflow);
-          }
-        }
+        for (int x = 0; x < S; ++x) stage[pos * S + x] = key[x];
       }
-      if (act && res == kFull)
-        atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagTableFull);
+      n_new += static_cast<uint32_t>(__popcll(m));
+    }
+    if (__ballot(full) && lane == 0)
+      atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagTableFull);
+    wave_lds_sync();
+    if (n_new) {
+      unsigned long long base = 0;
+      if (lane == 0)
+        base = atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[0]),
+                         static_cast<unsigned long long>(n_new));
+      base = __shfl(base, 0, 64);
+      if (lane == 0 && base + n_new > j.cap_out)
+        atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagFrontierOverflow);
+      for (uint32_t k = lane; k < n_new * S; k += 64)
+        if (base * S + k < j.cap_out * S) j.frontier_out[base * S + k] = stage[k];
     }
     wave_lds_sync();
   }
