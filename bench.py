@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-explore", action="store_true", help="skip the exploration leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--probe-gib", type=int, action="append", default=[],
@@ -368,6 +369,27 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
             pool.append((nt, r.n_states))
         reqs = [pool[rng.randrange(len(pool))] for _ in range(n_req)]
         total_states = sum(sz for _, sz in reqs)
+        # one exploration call per request (gx_explore into a resident table of
+        # the request's network, cleared first): the one-launch-per-instance
+        # reference
+        tables = {}
+        for nt, sz in pool:
+            tables[id(nt)] = gx.Table(gx.network_words(nt), 32, max(64, int(sz * 2.5)),
+                                      subgroup=8, keys_per_subgroup=1, max_hashes=16)
+            gx.explore(nt, tables[id(nt)])  # sizes its resident buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for nt, sz in reqs:
+            t = tables[id(nt)]
+            t.clear()
+            gx.explore(nt, t)
+        torch.cuda.synchronize()
+        single = time.perf_counter() - t0
+        for t in tables.values():
+            t.close()
+        out.append({"served": "one gx_explore call per request, back to back",
+                    "requests": n_req, "seconds": round(single, 3),
+                    "states_per_s": round(total_states / single)})
         # back to back, one at a time: the service rate
         t0 = time.perf_counter()
         for nt, sz in reqs:
@@ -405,7 +427,8 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
                         "p50_latency_s": round(lat[len(lat) // 2], 4),
                         "p99_latency_s": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
                         "wrong_results": bad, "active_peak": stt["active_peak"],
-                        "retried": stt["retried"]})
+                        "retried": stt["retried"],
+                        "vs_one_call_per_request": round(single / wall, 2)})
     return out
 
 
@@ -582,7 +605,17 @@ def main():
     if not args.no_explore:
         out["explore"] = run_explore_leg(gx, torch, W)
     if not args.no_batch:
-        out.update(run_batch(gx, torch, W, args.batch_n))
+        out.update(run_batch(gx, torch, W, args.batch_n, B=args.batch_bucket,
+                             G=args.batch_subgroup, U=args.batch_kps))
+    if not args.no_serve:
+        rows = run_serve(gx, torch, W, args.serve_n, rates=(1.0, 4.0))
+        out["served"] = {
+            "workload": ("Poisson request streams (token rings of 7-15 nodes and two random "
+                         "networks, 1e4-1.4e8 states, 1-4 words), bound declared 1.25x"),
+            "one_call_per_request_states_per_s": rows[0]["states_per_s"],
+            "rates": [{k: r[k] for k in ("rate_per_s", "states_per_s", "p50_latency_s",
+                                         "p99_latency_s", "wrong_results",
+                                         "vs_one_call_per_request")} for r in rows[2:]]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

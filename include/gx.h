@@ -290,7 +290,7 @@ typedef struct {
   uint32_t max_hashes;        /* H; 0 -> 8                                     */
   uint32_t bucket_words;      /* 0 -> autotuned per instance, else 8|16|32|64 */
   uint32_t subgroup;          /* 0 -> autotuned per instance, else 8|16        */
-  uint32_t keys_per_subgroup; /* 0 -> autotuned per instance, else 1|2         */
+  uint32_t keys_per_subgroup; /* 0 -> 1, else 1|2                             */
   uint32_t use_graph;         /* nonzero: gx_batch_create captures a whole run
                                  (clears, resets and every launch) in a hipGraph
                                  and gx_batch_run replays it                   */
@@ -362,7 +362,7 @@ typedef struct {
   uint64_t hash_seed;         /* 0 -> the default seed                         */
   uint32_t bucket_words;      /* 0 -> autotuned per slot width, else 8..64     */
   uint32_t subgroup;          /* 0 -> autotuned, else 8|16                     */
-  uint32_t keys_per_subgroup; /* 0 -> autotuned, else 1|2                      */
+  uint32_t keys_per_subgroup; /* 0 -> 1, else 1|2                             */
   uint32_t reserved;
 } gx_server_opts;
 

@@ -320,7 +320,11 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
       }
       B = B ? B : tb;
       G = G ? G : tg;
-      U = U ? U : tu;
+      // one key in flight per subgroup unless asked: the autotuner times the
+      // isolated find-or-put, where more keys in flight pay off, but in the
+      // exploration kernels they cost a wave per SIMD of occupancy
+      (void)tu;
+      U = U ? U : 1;
     }
     const uint32_t S = gx::slot_words(words[i]);
     if (B < 2 * S) B = 2 * S;

@@ -465,7 +465,11 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
       }
       B = B ? B : tb;
       G = G ? G : tg;
-      U = U ? U : tu;
+      // one key in flight per subgroup unless asked: the autotuner times the
+      // isolated find-or-put, where more keys in flight pay off, but in the
+      // exploration kernels they cost a wave per SIMD of occupancy
+      (void)tu;
+      U = U ? U : 1;
     }
     if (B < 2 * S) B = 2 * S;
     s->cfg[S][0] = B;
