@@ -160,30 +160,61 @@ __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) 
   }
 }
 
-// Write every successor of this state, in the order emit_successors numbers
-// them, to out[k * S] (global memory; one lane writes a contiguous run).
+// Write every successor of this state (the successors emit_successors
+// numbers, not necessarily in its order) to out[k * S] (global memory; one
+// lane writes a contiguous run).
 template <int S>
 __device__ __forceinline__ void emit_all(const uint32_t* img, const uint32_t (&sw)[S],
                                          uint32_t* out) {
   const uint32_t P = img[0], R = img[1];
   uint32_t* o = out;
+  // Targets are read from LDS four at a time before any successor of the
+  // group is formed, so one LDS round trip serves up to four successors.
+  auto emit_range = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t s1) {
+    for (uint32_t t = s0; t < s1; t += 4) {
+      uint32_t d[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) d[k] = img[min(t + k, s1 - 1)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (t + k < s1) {
+          uint32_t succ[S];
+#pragma unroll
+          for (int x = 0; x < S; ++x) succ[x] = from[x];
+          set_field<S>(succ, f, d[k]);
+          store_slot<S>(o, succ);
+          o += S;
+        }
+      }
+    }
+  };
   for (uint32_t p = 0; p < P; ++p) {
     const uint32_t f = img[4 + p];
     const uint32_t l = get_field<S>(sw, f);
     const uint32_t ob = img[4 + P + p];
-    const uint32_t s0 = img[ob + l], s1 = img[ob + l + 1];
-    for (uint32_t t = s0; t < s1; ++t) {
-      uint32_t succ[S];
-#pragma unroll
-      for (int x = 0; x < S; ++x) succ[x] = sw[x];
-      set_field<S>(succ, f, img[t]);
-      store_slot<S>(o, succ);
-      o += S;
-    }
+    emit_range(sw, f, img[ob + l], img[ob + l + 1]);
   }
   for (uint32_t r = 0; r < R; ++r) {
     const uint32_t rb = img[4 + 2 * P + r];
     const uint32_t np = img[rb];
+    if (np == 2) {
+      // two participants (the common rendezvous): their target ranges are
+      // read once, the combinations enumerated by two nested loops
+      const uint32_t f0 = img[4 + img[rb + 1]], ob0 = img[rb + 2];
+      const uint32_t f1 = img[4 + img[rb + 3]], ob1 = img[rb + 4];
+      const uint32_t l0 = get_field<S>(sw, f0), l1 = get_field<S>(sw, f1);
+      const uint32_t a0 = img[ob0 + l0], e0 = img[ob0 + l0 + 1];
+      const uint32_t a1 = img[ob1 + l1], e1 = img[ob1 + l1 + 1];
+      if (a1 == e1) continue;
+      for (uint32_t t0 = a0; t0 < e0; ++t0) {
+        uint32_t mid[S];
+#pragma unroll
+        for (int x = 0; x < S; ++x) mid[x] = sw[x];
+        set_field<S>(mid, f0, img[t0]);
+        emit_range(mid, f1, a1, e1);
+      }
+      continue;
+    }
     uint32_t prod = 1;
     for (uint32_t i = 0; i < np && prod; ++i) {
       const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
