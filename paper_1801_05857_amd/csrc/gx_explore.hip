@@ -212,7 +212,7 @@ namespace {
 // One slice of a level: successor generation, then find-or-put-and-append.
 hipError_t launch_slice(const gx_table* t, const GenArgs& g, uint32_t grid, size_t lds,
                         const AppendArgs& ap, uint32_t cus, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(g.ctr + 5, 0, sizeof(uint64_t), s);
+  hipError_t e = hipMemsetAsync(g.ctr + kCtrSucc * kCtrSpread, 0, sizeof(uint64_t), s);
   if (e != hipSuccess) return e;
   switch (t->S) {
     case 1:
@@ -330,7 +330,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
                  stream, img_stride) != hipSuccess)
       return GX_ENOMEM;
   }
-  if (!eb.ctr && (hipMalloc(&eb.ctr, 8 * sizeof(uint64_t)) != hipSuccess ||
+  constexpr size_t kCtrWords = gx::kCtrCount * gx::kCtrSpread;
+  if (!eb.ctr && (hipMalloc(&eb.ctr, kCtrWords * sizeof(uint64_t)) != hipSuccess ||
                   hipMalloc(&eb.status, 8) != hipSuccess ||
                   hipMalloc(&eb.key, 4 * sizeof(uint32_t)) != hipSuccess)) {
     (void)hipGetLastError();
@@ -342,13 +343,15 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
 
   uint32_t init[4] = {0, 0, 0, 0};
   gx::pack_host(ni, ni.initial.data(), init);
-  uint64_t ctr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t ctr_raw[kCtrWords] = {};
+  // the level's counters, spread over cache lines on the device
+  auto ctr = [&](uint32_t k) { return ctr_raw[k * gx::kCtrSpread]; };
   if (hipMemcpyAsync(eb.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
                      stream) != hipSuccess ||
       hipMemcpyAsync(eb.f[0], init, state_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(eb.key, init, t->w * sizeof(uint32_t), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
-      hipMemsetAsync(eb.ctr, 0, 8 * sizeof(uint64_t), stream) != hipSuccess)
+      hipMemsetAsync(eb.ctr, 0, kCtrWords * sizeof(uint64_t), stream) != hipSuccess)
     return GX_EDEVICE;
   // the initial state must be new, i.e. the table must not hold it yet
   if (gx::launch_find_or_put(t, eb.key, 1, eb.status, nullptr, stream) != hipSuccess)
@@ -369,7 +372,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   gx::AppendArgs ap;
   ap.t = t->dev();
   ap.keys = nullptr;
-  ap.n_keys = eb.ctr + 5;
+  ap.n_keys = eb.ctr + gx::kCtrSucc * gx::kCtrSpread;
   ap.ctr = eb.ctr;
   const uint32_t dedup_words =
       g.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
@@ -380,11 +383,12 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
   auto read_ctr = [&]() -> gx_status {
-    if (hipMemcpyAsync(ctr, eb.ctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    if (hipMemcpyAsync(ctr_raw, eb.ctr, sizeof(ctr_raw), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return GX_EDEVICE;
-    if (ctr[3] & gx::kFlagTableFull) return GX_ETABLEFULL;
-    if (ctr[3] & gx::kFlagFrontierOverflow) return GX_ENOMEM;
+    if (ctr(gx::kCtrFlags) & gx::kFlagTableFull) return GX_ETABLEFULL;
+    if (ctr(gx::kCtrFlags) & gx::kFlagFrontierOverflow) return GX_ENOMEM;
     return GX_OK;
   };
 
@@ -402,7 +406,9 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   constexpr uint64_t kMaxRoom = 1ull << 28;    // states of frontier room one slice may claim
   while (n_in > 0) {
     const int nxt = cur ^ 1;
-    if (hipMemsetAsync(eb.ctr, 0, sizeof(uint64_t), stream) != hipSuccess) return GX_EDEVICE;
+    if (hipMemsetAsync(eb.ctr + gx::kCtrTail * gx::kCtrSpread, 0, sizeof(uint64_t), stream) !=
+        hipSuccess)
+      return GX_EDEVICE;
     uint64_t tail_known = 0, bound = 0, dead_bound = dead_known, pos = 0;
     while (pos < n_in) {
       // full slices, but never more than kMaxRoom states of frontier room
@@ -419,8 +425,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       if (std::min<uint64_t>(f_room(), d_room()) < want) {
         if (bound != tail_known || dead_bound != dead_known) {
           if ((s = read_ctr()) != GX_OK) return s;
-          tail_known = bound = ctr[0];
-          dead_known = dead_bound = ctr[1];
+          tail_known = bound = ctr(gx::kCtrTail);
+          dead_known = dead_bound = ctr(gx::kCtrDead);
         }
         if (f_room() < want) {
           s = grow_buf(&eb.f[nxt], &eb.f_cap[nxt], bound + want * max_succ, tail_known, max_cap);
@@ -466,12 +472,12 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       dead_bound += run;
     }
     if ((s = read_ctr()) != GX_OK) return s;
-    dead_known = ctr[1];
-    n_in = ctr[0];
+    dead_known = ctr(gx::kCtrDead);
+    n_in = ctr(gx::kCtrTail);
     if (n_in) levels.push_back(n_in);
     cur = nxt;
   }
-  const uint64_t n_dead = ctr[1];
+  const uint64_t n_dead = ctr(gx::kCtrDead);
   if (n_dead > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;
   std::vector<uint32_t> raw(n_dead * S);
   if (n_dead && hipMemcpy(raw.data(), eb.dead, raw.size() * sizeof(uint32_t),
@@ -499,13 +505,13 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   for (uint64_t i = 0; i < n_dead; ++i)
     for (uint32_t k = 0; k < t->w; ++k) dd[i * t->w + k] = dl[i][k];
   out->n_states = n_states;
-  out->n_transitions = ctr[2];
+  out->n_transitions = ctr(gx::kCtrTrans);
   out->words_per_state = t->w;
   out->n_levels = static_cast<uint32_t>(levels.size());
   out->level_counts = lv;
   out->n_deadlocks = n_dead;
   out->deadlocks = dd;
-  out->local_duplicates = ctr[4];
+  out->local_duplicates = ctr(gx::kCtrDups);
   return GX_OK;
 }
 

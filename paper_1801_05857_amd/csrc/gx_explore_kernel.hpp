@@ -457,47 +457,51 @@ struct GenArgs {
   uint64_t succ_cap;    // keys
   uint32_t* dead;
   uint64_t dead_cap;
-  uint64_t* ctr;  // [1] deadlocks [2] transitions [3] flags [4] local duplicates [5] successors written
+  uint64_t* ctr;  // kCtrCount counters, kCtrSpread words apart (see ctr_at)
   uint32_t dedup;
 };
 
-// 64 frontier states [first, first + 64) of the slice: successors to a.succ.
+// Counters of the two-kernel level live kCtrSpread words apart, each on a
+// cache line of its own: every wavefront of a level updates some of them, and
+// counters sharing a line would serialise at one L2 atomic unit.
+constexpr uint32_t kCtrSpread = 16;
+enum : uint32_t { kCtrTail = 0, kCtrDead = 1, kCtrTrans = 2, kCtrFlags = 3, kCtrDups = 4,
+                  kCtrSucc = 5, kCtrCount = 6 };
+
+__device__ __forceinline__ unsigned long long* ctr_at(uint64_t* ctr, uint32_t k) {
+  return reinterpret_cast<unsigned long long*>(ctr + k * kCtrSpread);
+}
+
+// Load, count and deadlock-check this lane's frontier state.
 template <int S>
-__device__ inline void gen_wave(const GenArgs& a, const uint32_t* img, uint32_t* stage,
-                                uint32_t* dtab, uint64_t first) {
-  constexpr uint32_t CAP = kStageWords / 4 / S;  // staged successors per chunk
-  const int lane = __lane_id();
-  const uint64_t i = first + lane;
+__device__ __forceinline__ uint32_t gen_count(const GenArgs& a, const uint32_t* img, uint64_t i,
+                                              uint32_t (&sw)[S]) {
   const bool has = i < a.n_in;
-  uint32_t sw[S];
 #pragma unroll
   for (int x = 0; x < S; ++x) sw[x] = 0;
   if (has) load_slot<S>(a.frontier_in + i * S, sw);
   const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
   if (has && c == 0) {
-    const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[1]), 1ull);
+    const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
     if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
   }
+  return c;
+}
+
+// With the duplicate filter: 64 frontier states [first, first + 64) expanded
+// chunk by chunk through the wavefront's LDS staging; repeats within a chunk
+// are dropped, the rest copied out with coalesced stores.
+template <int S>
+__device__ inline void gen_wave_filtered(const GenArgs& a, const uint32_t* img, uint32_t* stage,
+                                         uint32_t* dtab, uint64_t first) {
+  constexpr uint32_t CAP = kStageWords / 4 / S;  // staged successors per chunk
+  const int lane = __lane_id();
+  uint32_t sw[S];
+  const uint32_t c = gen_count<S>(a, img, first + lane, sw);
   uint32_t total = 0;
   const uint32_t off = wave_exclusive_scan(c, &total);
   if (lane == 0 && total)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[2]), static_cast<unsigned long long>(total));
-  if (!dtab) {
-    // no filter: every lane writes its own successors straight to their
-    // place in the buffer, one pass over its transitions
-    unsigned long long base = 0;
-    if (lane == 0 && total)
-      base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[5]),
-                       static_cast<unsigned long long>(total));
-    base = __shfl(base, 0, 64);
-    if (base + total > a.succ_cap) {
-      if (lane == 0)  // cannot happen with the host's bound; refuse rather than overrun
-        atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
-    } else if (c) {
-      emit_all<S>(img, sw, a.succ + (base + off) * S);
-    }
-    return;
-  }
+    atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(total));
   for (uint32_t lo = 0; lo < total; lo += CAP) {
     const uint32_t hi = min(total, lo + CAP);
     if (c && off < hi && off + c > lo)
@@ -507,17 +511,15 @@ __device__ inline void gen_wave(const GenArgs& a, const uint32_t* img, uint32_t*
     const uint32_t n_st = hi - lo;
     uint32_t dupmask = 0;
     const uint32_t wd = dedup_chunk<S>(dtab, stage, n_st, &dupmask);
-    if (lane == 0 && wd) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[4]), wd);
+    if (lane == 0 && wd) atomicAdd(ctr_at(a.ctr, kCtrDups), static_cast<unsigned long long>(wd));
     const uint32_t n_keep = n_st - wd;
     unsigned long long base = 0;
     if (lane == 0 && n_keep)
-      base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[5]),
-                       static_cast<unsigned long long>(n_keep));
+      base = atomicAdd(ctr_at(a.ctr, kCtrSucc), static_cast<unsigned long long>(n_keep));
     base = __shfl(base, 0, 64);
     if (base + n_keep > a.succ_cap) {
       // cannot happen with the host's bound; refuse rather than overrun
-      if (lane == 0)
-        atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
+      if (lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagFrontierOverflow);
     } else {
       uint32_t kept = 0;  // kept successors of earlier rounds
       for (uint32_t r0 = 0, r = 0; r0 < n_st; r0 += 64, ++r) {
@@ -540,16 +542,50 @@ __device__ inline void gen_wave(const GenArgs& a, const uint32_t* img, uint32_t*
 template <int S>
 __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   extern __shared__ uint32_t smem[];
+  __shared__ uint32_t wave_total[4];
+  __shared__ unsigned long long group_base;
   uint32_t* img = smem;
-  // staging and filter space only with the duplicate filter
-  uint32_t* stage = smem + a.img_stride + (threadIdx.x >> 6) * (kStageWords / 4);
-  uint32_t* dtab = a.dedup ? smem + a.img_stride + kStageWords +
-                                 (threadIdx.x >> 6) * dedup_entries<S>()
-                           : nullptr;
   for (uint32_t k = threadIdx.x; k < a.img_words; k += 256) img[k] = a.img[k];
   __syncthreads();
+  const int wave = static_cast<int>(threadIdx.x >> 6);
   const uint64_t first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
-  if (first < a.n_in) gen_wave<S>(a, img, stage, dtab, first);
+  if (a.dedup) {
+    // staging and filter space only with the duplicate filter
+    uint32_t* stage = smem + a.img_stride + wave * (kStageWords / 4);
+    uint32_t* dtab = smem + a.img_stride + kStageWords + wave * dedup_entries<S>();
+    if (first < a.n_in) gen_wave_filtered<S>(a, img, stage, dtab, first);
+    return;
+  }
+  // No filter: one atomic add per workgroup reserves the room of all its
+  // successors; every lane then writes its own successors, a contiguous run,
+  // in one pass over its transitions.
+  const int lane = __lane_id();
+  uint32_t sw[S];
+  const uint32_t c = gen_count<S>(a, img, first + lane, sw);
+  uint32_t total = 0;
+  const uint32_t off = wave_exclusive_scan(c, &total);
+  if (lane == 0) wave_total[wave] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t t = static_cast<uint64_t>(wave_total[0]) + wave_total[1] + wave_total[2] +
+                       wave_total[3];
+    unsigned long long b = 0;
+    if (t) {
+      b = atomicAdd(ctr_at(a.ctr, kCtrSucc), static_cast<unsigned long long>(t));
+      atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(t));
+      if (b + t > a.succ_cap) {
+        // cannot happen with the host's bound; refuse rather than overrun
+        atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagFrontierOverflow);
+        b = ~0ull;
+      }
+    }
+    group_base = b;
+  }
+  __syncthreads();
+  uint64_t base = group_base;
+  if (base == ~0ull || c == 0) return;
+  for (int w = 0; w < wave; ++w) base += wave_total[w];
+  emit_all<S>(img, sw, a.succ + (base + off) * S);
 }
 
 struct AppendArgs {
@@ -559,7 +595,7 @@ struct AppendArgs {
   const uint64_t* n_keys;  // device memory: the number of keys (clamped to keys_cap)
   uint32_t* frontier_out;
   uint64_t cap_out;        // states
-  uint64_t* ctr;           // [0] next-frontier tail [3] flags
+  uint64_t* ctr;           // the level's counters (see ctr_at)
 };
 
 constexpr uint32_t kAppendKeys = 256;  // NEW keys a wavefront gathers in LDS
@@ -571,11 +607,9 @@ __device__ inline void append_flush(const AppendArgs& a, const uint32_t* buf, ui
   if (cnt == 0) return;
   const int lane = __lane_id();
   unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctr[0]),
-                                  static_cast<unsigned long long>(cnt));
+  if (lane == 0) base = atomicAdd(ctr_at(a.ctr, kCtrTail), static_cast<unsigned long long>(cnt));
   base = __shfl(base, 0, 64);
-  if (lane == 0 && base + cnt > a.cap_out)
-    atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagFrontierOverflow);
+  if (lane == 0 && base + cnt > a.cap_out) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagFrontierOverflow);
   for (uint32_t k = lane; k < cnt; k += 64) {
     if (base + k < a.cap_out) {
       uint32_t key[S];
@@ -619,8 +653,7 @@ __global__ __launch_bounds__(256) void append_kernel(AppendArgs a) {
   }
   wave_lds_sync();
   append_flush<S>(a, buf, cnt);
-  if (__ballot(full) && lane == 0)
-    atomicOr(reinterpret_cast<unsigned long long*>(&a.ctr[3]), kFlagTableFull);
+  if (__ballot(full) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagTableFull);
   flush_stats(a.t, st, nullptr);
 }
 

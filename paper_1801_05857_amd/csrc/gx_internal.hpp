@@ -19,7 +19,7 @@ struct gx_explore_buffers {
   uint64_t dead_cap = 0;  // states
   uint32_t* succ = nullptr;  // successors of a level slice, before the table probe
   uint64_t succ_cap = 0;     // states
-  uint64_t* ctr = nullptr;  // 8 counters
+  uint64_t* ctr = nullptr;  // level counters, one cache line each
   uint8_t* status = nullptr;
   uint32_t* key = nullptr;  // 4 words
 };
