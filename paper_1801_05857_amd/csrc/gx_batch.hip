@@ -546,11 +546,16 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
       const uint32_t i = c.members[k];
       const uint32_t w = b->w[i];
       const gx::BatchState& st = hs[k];
+      const uint64_t flags = st.ctr[gx::kCtrFlags * gx::kCtrSpread];
       gx_status s = GX_OK;
-      if (!st.done || hg.abort) s = GX_EDEVICE;
-      else if (st.ctr[3] & gx::kFlagTableFull) s = GX_ETABLEFULL;
-      else if (st.ctr[3]) s = GX_ENOMEM;
-      else if (per[k].size() != st.ctr[1]) s = GX_ENOMEM;  // deadlock records overflowed
+      if (!st.done || hg.abort)
+        s = GX_EDEVICE;
+      else if (flags & gx::kFlagTableFull)
+        s = GX_ETABLEFULL;
+      else if (flags)
+        s = GX_ENOMEM;
+      else if (per[k].size() != st.ctr[gx::kCtrDead * gx::kCtrSpread])
+        s = GX_ENOMEM;  // deadlock records overflowed
       inst_status[i] = s;
       if (s != GX_OK) continue;
       const uint32_t n_levels = st.level + 1;
@@ -572,7 +577,7 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
       for (size_t r = 0; r < dl.size(); ++r)
         for (uint32_t x = 0; x < w; ++x) D[r * w + x] = dl[r][x];
       outs[i].n_states = total;
-      outs[i].n_transitions = st.ctr[2];
+      outs[i].n_transitions = st.ctr[gx::kCtrTrans * gx::kCtrSpread];
       outs[i].words_per_state = w;
       outs[i].n_levels = n_levels;
       outs[i].level_counts = L;

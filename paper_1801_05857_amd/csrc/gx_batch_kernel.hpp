@@ -35,13 +35,15 @@ struct BatchInst {  // per instance, written by the host
 };
 
 struct BatchState {  // per instance, device-updated
-  uint64_t ctr[4];   // next tail, deadlocks, transitions, flags
+  uint64_t ctr[kCtrCount * kCtrSpread];  // counters, one cache line each (ctr_at)
   uint64_t n_in;     // states in the current level
   uint32_t level;    // index of the current level
   uint32_t cur;      // which frontier buffer holds it
   uint32_t done;
-  uint32_t pad[3];
+  uint32_t pad[27];  // the next instance's counters start on a fresh line
 };
+
+static_assert(sizeof(BatchState) % 128 == 0, "instance counters on their own cache lines");
 
 struct BatchEntry {
   uint32_t inst;
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(64) void batch_init_kernel(BatchArgs a) {
   const uint8_t r = find_or_put_lanes<S, B, G, U>(in.t, key, __lane_id() == 0, st);
   if (__lane_id() == 0 && r != kNew) {
     // table not empty of it, or full: the instance fails before its first level
-    atomicOr(reinterpret_cast<unsigned long long*>(&a.state[i].ctr[3]),
+    atomicOr(ctr_at(a.state[i].ctr, kCtrFlags),
              static_cast<unsigned long long>(r == kFull ? kFlagTableFull : kFlagFrontierOverflow));
   }
 }
@@ -205,25 +207,26 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
       if (fin == e->tiles) {
         // last tile of the level: publish the next level or finish
         __threadfence();
-        const uint64_t n_next = __hip_atomic_load(&bs.ctr[0], __ATOMIC_RELAXED,
+        const uint64_t n_next = __hip_atomic_load(&bs.ctr[kCtrTail * kCtrSpread], __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t flags = __hip_atomic_load(&bs.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t flags = __hip_atomic_load(&bs.ctr[kCtrFlags * kCtrSpread], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
         bool finished = flags != 0 || n_next == 0;
         if (!finished) {
           if (bs.level + 1 >= in.max_levels) {
-            atomicOr(reinterpret_cast<unsigned long long*>(&bs.ctr[3]), kFlagLevelsOverflow);
+            atomicOr(ctr_at(bs.ctr, kCtrFlags), kFlagLevelsOverflow);
             finished = true;
           } else {
             in.levels[bs.level + 1] = n_next;
             const uint32_t slot = atomicAdd(&a.g->tail, 1u);
             if (slot >= a.queue_cap) {
-              atomicOr(reinterpret_cast<unsigned long long*>(&bs.ctr[3]), kFlagQueueOverflow);
+              atomicOr(ctr_at(bs.ctr, kCtrFlags), kFlagQueueOverflow);
               finished = true;
             } else {
               bs.level += 1;
               bs.cur ^= 1u;
               bs.n_in = n_next;
-              bs.ctr[0] = 0;
+              bs.ctr[kCtrTail * kCtrSpread] = 0;
               BatchEntry* ne = &a.queue[slot];
               ne->inst = iid;
               ne->tiles = static_cast<uint32_t>((n_next + 255) / 256);

@@ -262,9 +262,21 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// An exploration's counters live kCtrSpread words apart, each on a cache
+// line of its own: every wavefront of a level updates some of them, and
+// counters sharing a line would serialise at one L2 atomic unit.
+constexpr uint32_t kCtrSpread = 16;
+enum : uint32_t { kCtrTail = 0, kCtrDead = 1, kCtrTrans = 2, kCtrFlags = 3, kCtrDups = 4,
+                  kCtrSucc = 5, kCtrCount = 6 };
+
+__device__ __forceinline__ unsigned long long* ctr_at(uint64_t* ctr, uint32_t k) {
+  return reinterpret_cast<unsigned long long*>(ctr + k * kCtrSpread);
+}
+
 // One wavefront's share of a BFS level: frontier states [first, first + 64)
 // (those below n_in) of one exploration.  Counters of that exploration:
-// ctr[0] next-frontier tail, ctr[1] deadlocks, ctr[2] transitions, ctr[3] flags.
+// Counters of that exploration: ctr_at(ctr, kCtrTail / kCtrDead / kCtrTrans /
+// kCtrFlags / kCtrDups).
 struct WaveJob {
   TableDev t;
   const uint32_t* img;  // network image, in LDS
@@ -354,8 +366,8 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
     const uint32_t c = has ? count_successors<S>(j.img, sw) : 0u;
     if (has && c == 0) {
       const uint64_t d = atomicAdd(reinterpret_cast<unsigned long long*>(j.dead_ctr), 1ull);
-      if (j.dead_ctr != &j.ctr[1])
-        atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[1]), 1ull);
+      if (j.dead_ctr != reinterpret_cast<uint64_t*>(ctr_at(j.ctr, kCtrDead)))
+        atomicAdd(ctr_at(j.ctr, kCtrDead), 1ull);
       if (d < j.dead_cap) {
 #pragma unroll
         for (int x = 0; x < S; ++x) j.dead[d * S + x] = sw[x];
@@ -364,7 +376,7 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
     }
     (void)wave_exclusive_scan(c, &total);
     if (lane == 0 && total)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[2]),
+      atomicAdd(ctr_at(j.ctr, kCtrTrans),
                 static_cast<unsigned long long>(total));
   }
 
@@ -390,7 +402,7 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
     uint32_t dupmask = 0;
     if (j.dtab) {
       const uint32_t wd = dedup_chunk<S>(j.dtab, stage, n_st, &dupmask);
-      if (lane == 0 && wd) atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[4]), wd);
+      if (lane == 0 && wd) atomicAdd(ctr_at(j.ctr, kCtrDups), static_cast<unsigned long long>(wd));
     }
     // NEW keys are compacted in place to the front of the staging area (a
     // round writes below the end of the keys it has read), then moved to the
@@ -416,16 +428,16 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
       n_new += static_cast<uint32_t>(__popcll(m));
     }
     if (__ballot(full) && lane == 0)
-      atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagTableFull);
+      atomicOr(ctr_at(j.ctr, kCtrFlags), kFlagTableFull);
     wave_lds_sync();
     if (n_new) {
       unsigned long long base = 0;
       if (lane == 0)
-        base = atomicAdd(reinterpret_cast<unsigned long long*>(&j.ctr[0]),
+        base = atomicAdd(ctr_at(j.ctr, kCtrTail),
                          static_cast<unsigned long long>(n_new));
       base = __shfl(base, 0, 64);
       if (lane == 0 && base + n_new > j.cap_out)
-        atomicOr(reinterpret_cast<unsigned long long*>(&j.ctr[3]), kFlagFrontierOverflow);
+        atomicOr(ctr_at(j.ctr, kCtrFlags), kFlagFrontierOverflow);
       for (uint32_t k = lane; k < n_new * S; k += 64)
         if (base * S + k < j.cap_out * S) j.frontier_out[base * S + k] = stage[k];
     }
@@ -460,17 +472,6 @@ struct GenArgs {
   uint64_t* ctr;  // kCtrCount counters, kCtrSpread words apart (see ctr_at)
   uint32_t dedup;
 };
-
-// Counters of the two-kernel level live kCtrSpread words apart, each on a
-// cache line of its own: every wavefront of a level updates some of them, and
-// counters sharing a line would serialise at one L2 atomic unit.
-constexpr uint32_t kCtrSpread = 16;
-enum : uint32_t { kCtrTail = 0, kCtrDead = 1, kCtrTrans = 2, kCtrFlags = 3, kCtrDups = 4,
-                  kCtrSucc = 5, kCtrCount = 6 };
-
-__device__ __forceinline__ unsigned long long* ctr_at(uint64_t* ctr, uint32_t k) {
-  return reinterpret_cast<unsigned long long*>(ctr + k * kCtrSpread);
-}
 
 // Load, count and deadlock-check this lane's frontier state.
 template <int S>

@@ -21,7 +21,7 @@ struct ServeJob {
   uint64_t cap_out;
   uint32_t* dead;
   uint64_t dead_cap;
-  uint64_t* ctr;        // next tail, deadlocks, transitions, flags
+  uint64_t* ctr;        // the job's counters (ctr_at)
   uint64_t tile_begin;  // first tile of this job in the step
 };
 
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void serve_step_kernel(ServeArgs a) {
   j.dead_tag = nullptr;
   j.tag = 0;
   j.dead_cap = jb.dead_cap;
-  j.dead_ctr = &jb.ctr[1];
+  j.dead_ctr = reinterpret_cast<uint64_t*>(ctr_at(jb.ctr, kCtrDead));
   j.ctr = jb.ctr;
   j.dtab = nullptr;
   LaneStats st;

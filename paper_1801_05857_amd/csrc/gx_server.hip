@@ -41,6 +41,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr uint32_t kMaxAttempts = 12;
+// a job's counters: kCtrCount counters kCtrSpread words apart (one cache line each)
+constexpr uint64_t kSlotCtrWords = uint64_t(kCtrCount) * kCtrSpread;
 
 struct Request {
   uint64_t id = 0;
@@ -233,7 +235,8 @@ void admit(gx_server* s) {
                              s->stream) == hipSuccess &&
               hipMemcpyAsync(t->eb.key, init, r->w * sizeof(uint32_t), hipMemcpyHostToDevice,
                              s->stream) == hipSuccess &&
-              hipMemsetAsync(s->d_ctr + 4 * j.slot, 0, 4 * sizeof(uint64_t), s->stream) ==
+              hipMemsetAsync(s->d_ctr + kSlotCtrWords * j.slot, 0, kSlotCtrWords * sizeof(uint64_t),
+                             s->stream) ==
                   hipSuccess &&
               launch_find_or_put(t, t->eb.key, 1, t->eb.status, nullptr, s->stream) == hipSuccess &&
               hipMemcpyAsync(s->d_img + static_cast<uint64_t>(j.slot) * kImgMaxWords,
@@ -347,7 +350,7 @@ void step_loop(gx_server* s) {
         x.cap_out = j.t->eb.f_cap[j.cur ^ 1];
         x.dead = j.t->eb.dead;
         x.dead_cap = j.t->eb.dead_cap;
-        x.ctr = s->d_ctr + 4 * j.slot;
+        x.ctr = s->d_ctr + kSlotCtrWords * j.slot;
         x.tile_begin = tiles;
         tiles += (j.n_in + 255) / 256;
         img_max = std::max<uint32_t>(img_max, x.img_words);
@@ -373,7 +376,7 @@ void step_loop(gx_server* s) {
       // the host copy of hj must outlive the transfer
       if (e != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) ok = false;
     }
-    ctr.assign(4 * static_cast<size_t>(s->max_active), 0);
+    ctr.assign(kSlotCtrWords * static_cast<size_t>(s->max_active), 0);
     if (ok && hipMemcpy(ctr.data(), s->d_ctr, ctr.size() * sizeof(uint64_t),
                         hipMemcpyDeviceToHost) != hipSuccess)
       ok = false;
@@ -385,19 +388,20 @@ void step_loop(gx_server* s) {
         finish_job(s, k, GX_EDEVICE, 0, 0);
         continue;
       }
-      const uint64_t* c = &ctr[4 * j.slot];
-      const uint64_t flags = c[3], n_next = c[0];
+      const uint64_t* c = &ctr[kSlotCtrWords * j.slot];
+      const uint64_t flags = c[kCtrFlags * kCtrSpread], n_next = c[kCtrTail * kCtrSpread];
       if (flags & kFlagTableFull) {
         finish_job(s, k, GX_ETABLEFULL, 0, 0);
       } else if (flags) {
         finish_job(s, k, GX_ENOMEM, 0, 0);
       } else if (n_next == 0) {
-        finish_job(s, k, GX_OK, c[2], c[1]);
+        finish_job(s, k, GX_OK, c[kCtrTrans * kCtrSpread], c[kCtrDead * kCtrSpread]);
       } else {
         j.levels.push_back(n_next);
         j.n_in = n_next;
         j.cur ^= 1;
-        if (hipMemsetAsync(s->d_ctr + 4 * j.slot, 0, sizeof(uint64_t), s->stream) != hipSuccess)
+        if (hipMemsetAsync(s->d_ctr + kSlotCtrWords * j.slot + kCtrTail * kCtrSpread, 0,
+                           sizeof(uint64_t), s->stream) != hipSuccess)
           finish_job(s, k, GX_EDEVICE, 0, 0);
       }
     }
@@ -483,7 +487,7 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
       hipMalloc(&s->d_jobs, 3ull * s->max_active * sizeof(gx::ServeJob)) != hipSuccess ||
       hipMalloc(&s->d_img, static_cast<uint64_t>(s->max_active) * gx::kImgMaxWords *
                                sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&s->d_ctr, 4ull * s->max_active * sizeof(uint64_t)) != hipSuccess) {
+      hipMalloc(&s->d_ctr, gx::kSlotCtrWords * s->max_active * sizeof(uint64_t)) != hipSuccess) {
     (void)hipGetLastError();
     gx::destroy_server(s);
     return GX_ENOMEM;
