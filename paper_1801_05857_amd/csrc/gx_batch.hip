@@ -93,7 +93,7 @@ struct gx_batch {
     uint32_t* dead = nullptr;
     uint32_t* dead_tag = nullptr;
     uint64_t dead_cap = 0;
-    uint64_t* stats = nullptr;
+    uint64_t* stats = nullptr;  // table counters the descriptors point at (not updated)
     uint32_t grid = 0;
     size_t lds = 0;
     hipStream_t side = nullptr;
@@ -168,9 +168,6 @@ hipError_t enqueue_run(gx_batch* b, hipStream_t stream) {
         (e = hipMemcpyAsync(c.g, c.g_init, sizeof(BatchGlobal), hipMemcpyDeviceToDevice,
                             c.side)) != hipSuccess)
       return e;
-    if ((e = fill_words(reinterpret_cast<uint32_t*>(c.stats), 2 * kNumCounters, 0, b->device,
-                        c.side)) != hipSuccess)
-      return e;
     BatchArgs a;
     a.inst = c.inst;
     a.state = c.state;
@@ -184,7 +181,6 @@ hipError_t enqueue_run(gx_batch* b, hipStream_t stream) {
     a.dead_tag = c.dead_tag;
     a.dead_cap = c.dead_cap;
     a.spin_limit = kSpinLimit;
-    a.stats = c.stats;
     a.init_states = c.init_states;
     switch (c.S) {
       case 1: e = batch_launch<1>(c.B, c.G, c.U, a, c.grid, c.lds, c.side); break;
