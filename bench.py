@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-explore", action="store_true", help="skip the exploration leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
+    ap.add_argument("--no-alpha9", action="store_true", help="skip the load factor 0.9 run")
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--probe-gib", type=int, action="append", default=[],
@@ -172,6 +173,62 @@ def cpu_baseline(target_s: float = 15.0):
     return {"value": round(n / dt / 1e6, 3), "unit": "Mops/s", "cores": 1, "kind": "oracle",
             "sample": f"std::unordered_set insertion of 2^{k + 1} two-word keys "
                       f"(2^{k} distinct, each twice, shuffled), one thread, {dt:.1f} s"}
+
+
+def random_read_ceiling(gx, torch, granule: int, gib: int = 2):
+    """Random reads of `granule` bytes per second over a `gib` GiB buffer
+    (gx_gather_probe): the achievable ceiling of one bucket probe."""
+    buf = torch.empty(gib << 28, dtype=torch.int32, device="cuda")
+    buf.fill_(1)
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    n_reads = max(1 << 24, (1 << 31) // granule)
+    gx.gather_probe(buf, granule, n_reads, 7, sink)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    gx.gather_probe(buf, granule, n_reads, 7, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = n_reads / (e0.elapsed_time(e1) * 1e-3)
+    del buf
+    torch.cuda.empty_cache()
+    return rate
+
+
+def run_tiny(gx, torch, W, reps=10):
+    """The tiny configuration (four 8-state cycles with two rendezvous, one
+    word, table of 2^16 words, buckets of 32): microseconds per exploration,
+    median of `reps` after warm-up."""
+    net = W.tiny_cycles()
+    t = gx.Table(1, 32, 1 << 16, subgroup=8, max_hashes=16)
+    times = []
+    for k in range(reps + 3):
+        t.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gx.explore(net, t)
+        if k >= 3:
+            times.append(time.perf_counter() - t0)
+    t.close()
+    times.sort()
+    return {"workload": "tiny: 4 cyclic processes of 8 states, 2 rendezvous, w=1, table 2^16 words",
+            "states": r.n_states, "levels": len(r.levels),
+            "us_per_explore": round(times[len(times) // 2] * 1e6, 1)}
+
+
+def cpu_explore_baseline(W):
+    """The oracle BFS (std::unordered_set, one thread) on the large workload's
+    family at a size it finishes in seconds (4 live states per process)."""
+    import oracle
+
+    net = W.large_random_network(live=4)
+    t0 = time.perf_counter()
+    r = oracle.explore(net)
+    dt = time.perf_counter() - t0
+    return {"value": round(r.n_states / dt), "unit": "states/s", "cores": 1, "kind": "oracle",
+            "sample": f"BFS of the large workload's family with 4 live states per process "
+                      f"({r.n_states} states, {r.n_transitions} transitions), one thread, "
+                      f"{dt:.1f} s"}
 
 
 def explore_bytes_per_state(f: float, B: int, S: int) -> float:
@@ -600,6 +657,20 @@ def main():
         "find_or_put_Mops_per_s_kernel": round(n / (r["fop_ms"] * 1e-3) / 1e6, 1),
         "clear_ms": round(r["clear_ms"], 4),
     }
+    # the achievable random-read rate at the bucket's size, the second
+    # denominator of the roofline
+    ceil = random_read_ceiling(gx, torch, max(4 * args.bucket, GRANULE))
+    out["roofline"]["random_read_ceiling"] = {
+        "granule_bytes": max(4 * args.bucket, GRANULE), "G_reads_per_s": round(ceil / 1e9, 2),
+        "probes_per_s_frac": round(n * r["probes_per_op"] / (r["fop_ms"] * 1e-3) / ceil, 4)}
+    if args.alpha == 0.5 and not args.no_alpha9:
+        r9 = run_fop(gx, torch, keys, n_distinct, args.bucket, args.subgroup, args.kps, 0.9, 128,
+                     2, 1)
+        out["load_factor_0.9"] = {
+            "Mops_per_s_kernel": round(n / (r9["fop_ms"] * 1e-3) / 1e6, 1),
+            "probes_per_op": round(r9["probes_per_op"], 4), "max_hash_index": r9["max_hash_index"],
+            "full": r9["full"], "max_hashes": 128, "table_slots": r9["n_slots"]}
+    out["tiny"] = run_tiny(gx, torch, W)
     del keys
     torch.cuda.empty_cache()
     if not args.no_explore:
@@ -618,6 +689,8 @@ def main():
                                          "vs_one_call_per_request")} for r in rows[2:]]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        if not args.no_explore:
+            out["cpu_baseline"]["explore"] = cpu_explore_baseline(W)
     print(json.dumps(out), flush=True)
 
 
