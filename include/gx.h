@@ -248,10 +248,13 @@ typedef struct {
  *   opts   nullable.
  *   out    filled on success; free with gx_explore_result_free.
  *
- * Device buffers (frontiers, deadlock list, network image) are owned by the
- * table, allocated on first use and grown on demand; later explorations into
- * the same table reuse them.  A level is expanded in slices sized so that the
- * next frontier cannot overflow even if every successor were new.
+ * Device buffers (frontiers, successor buffer, deadlock list, network image)
+ * are owned by the table, allocated on first use and grown on demand; later
+ * explorations into the same table reuse them.  A level is expanded in
+ * slices sized so that neither the next frontier nor the successor buffer
+ * can overflow even if every successor were new; each slice is one
+ * successor-generation launch followed by one find-or-put-and-append launch
+ * on opts->hip_stream.
  *
  * Synchronous: returns when the exploration ends.
  * Errors: GX_EINVAL (invalid network, word count mismatch, non-empty table,
