@@ -456,6 +456,24 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
     }
     c.grid = static_cast<uint32_t>(per_cu) * static_cast<uint32_t>(cus);
   }
+  // Classes run concurrently on their own streams.  A persistent grid sized
+  // to the whole device would keep every other class's workgroups out until
+  // it drains, so each class gets the share of the device its instances'
+  // declared capacities claim of the total (at least one workgroup per CU).
+  if (b->classes.size() > 1) {
+    double total = 0;
+    std::vector<double> work(b->classes.size(), 0.0);
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+      for (uint32_t i : b->classes[k].members) work[k] += static_cast<double>(opts->capacity[i]);
+      total += work[k];
+    }
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+      auto& c = b->classes[k];
+      const double share = total > 0 ? work[k] / total : 1.0;
+      c.grid = std::max<uint32_t>(static_cast<uint32_t>(cus),
+                                  static_cast<uint32_t>(c.grid * share + 0.5));
+    }
+  }
   b->use_graph = opts->use_graph != 0;
   if (b->use_graph) {
     hipGraph_t graph = nullptr;
