@@ -21,7 +21,8 @@ def dev():
 
 
 def _mixed_networks(k):
-    nets = [W.fig1_producer_consumers(), W.tiny_cycles(), W.token_ring(5), W.token_ring(11)]
+    nets = [W.fig1_producer_consumers(), W.tiny_cycles(), W.token_ring(5), W.token_ring(11),
+            W.wide_rule(5, 4)]
     # networks with reachable deadlocks
     nets += [W.random_lts(s, 3 + s % 3, 8, 6, 2, 8, 0.5, 0.4) for s in (2, 8, 13, 14, 24)]
     for seed in range(k):

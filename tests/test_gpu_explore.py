@@ -171,3 +171,19 @@ def test_local_duplicate_filter_keeps_results(dev, which, B, G, U):
         assert s.lookups + got.local_duplicates == want.n_transitions + 1
     if which in ("tiny", "ring9"):
         assert got.local_duplicates > 0
+
+
+@pytest.mark.parametrize("P,k", [(4, 4), (6, 5)])
+@pytest.mark.parametrize("dedup", [False, True])
+def test_wide_rule_fan_out(dev, P, k, dedup):
+    """One state with k^P successors (a rule over every process): slices of
+    very different sizes, the general rule enumeration, many deadlocks."""
+    net = W.wide_rule(P, k)
+    want = oracle.explore(net, want_visited=True)
+    with gx.Table(want.words, 32, 2 * want.n_states, subgroup=8, max_hashes=64) as t:
+        got = gx.explore(net, t, local_dedup=dedup)
+        assert got.n_states == want.n_states == 1 + k ** P
+        assert got.levels.tolist() == want.levels.tolist()
+        assert got.n_transitions == want.n_transitions
+        assert np.array_equal(got.deadlocks, want.deadlocks)
+        assert np.array_equal(t.dump(), want.visited)

@@ -285,3 +285,14 @@ def test_bfs_prefix_matches_full_search():
                 assert pre.n_transitions < full.n_transitions
             else:
                 assert pre.n_transitions == full.n_transitions
+
+
+@pytest.mark.parametrize("P,k", [(2, 3), (4, 4), (6, 5)])
+def test_wide_rule_closed_form(P, k):
+    """One rule over every process, k choices each: the initial state has k^P
+    successors, all deadlocks (closed form)."""
+    r = oracle.explore(W.wide_rule(P, k))
+    assert r.n_states == 1 + k ** P
+    assert r.n_transitions == k ** P
+    assert r.levels.tolist() == [1, k ** P]
+    assert len(r.deadlocks) == k ** P

@@ -181,6 +181,18 @@ def random_lts(seed: int, n_procs: int, n_states, live, out_degree: int = 3,
                 name or f"random_s{seed}_p{n_procs}", seed=seed, live=lv.tolist())
 
 
+def wide_rule(n_procs: int = 6, k: int = 5) -> Network:
+    """One synchronisation rule over all n_procs processes: process p has
+    states 0..k, and k transitions labelled a from state 0 to states 1..k;
+    states 1..k have none.  The initial state therefore has k^n_procs
+    successors (one per choice of a transition in every process), all of
+    them deadlocks: 1 + k^n_procs states, k^n_procs transitions, levels
+    [1, k^n_procs].  A stress case for very wide per-state fan-out."""
+    trans = [[(0, 0, d) for d in range(1, k + 1)] for _ in range(n_procs)]
+    rules = np.zeros((1, n_procs), dtype=np.int32)
+    return _net([k + 1] * n_procs, [0] * n_procs, trans, 1, rules, f"wide_rule_{n_procs}x{k}")
+
+
 def large_random_network(live: int = 8) -> Network:
     """The large plain-path workload: 12 processes of 64 declared local states
     (6-bit fields, so 3-word vectors), out-degree 3 with uniform targets, a
