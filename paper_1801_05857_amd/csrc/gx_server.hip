@@ -318,7 +318,7 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
 }
 
 void step_loop(gx_server* s) {
-  std::vector<ServeJob> hj;
+  std::vector<ServeJob> hjs[3];  // per slot-width class; alive until the step's sync
   std::vector<uint64_t> ctr;
   while (true) {
     {
@@ -335,6 +335,7 @@ void step_loop(gx_server* s) {
     // one step over every active job, per slot-width class
     bool ok = true;
     for (uint32_t S : {1u, 2u, 4u}) {
+      std::vector<ServeJob>& hj = hjs[S == 1 ? 0 : S == 2 ? 1 : 2];
       hj.clear();
       uint64_t tiles = 0;
       uint32_t img_max = 0;
@@ -373,9 +374,12 @@ void step_loop(gx_server* s) {
           default: e = serve_launch<4>(c[0], c[1], c[2], a, static_cast<uint32_t>(tiles), lds, s->stream); break;
         }
       }
-      // the host copy of hj must outlive the transfer
-      if (e != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) ok = false;
+      if (e != hipSuccess) ok = false;
     }
+    // one synchronisation per step: the classes' launches follow each other
+    // on the stream without host round trips (the host copies in hjs stay
+    // alive until here)
+    if (hipStreamSynchronize(s->stream) != hipSuccess) ok = false;
     ctr.assign(kSlotCtrWords * static_cast<size_t>(s->max_active), 0);
     if (ok && hipMemcpy(ctr.data(), s->d_ctr, ctr.size() * sizeof(uint64_t),
                         hipMemcpyDeviceToHost) != hipSuccess)
