@@ -240,14 +240,18 @@ def explore_bytes_per_state(f: float, B: int, S: int) -> float:
     return f * (max(4 * B, GRANULE) + 2 * 4 * S) + 2 * 4 * S + GRANULE
 
 
-def run_explore_leg(gx, torch, W, live=8, B=32, G=8, U=1, slots=None):
+def run_explore_leg(gx, torch, W, live=8, B=0, G=0, U=1, slots=None):
     """States explored per second on the large plain-path workload (12
     processes of 64 declared states, 3-word vectors, 3.3e9 reachable states,
     192 GB table), with the table's buffers resident (a first exploration
-    sizes them), timed on the second exploration into the cleared table."""
+    sizes them), timed on the second exploration into the cleared table.
+    Bucket words and subgroup from the autotuner (0) unless given."""
     net = W.large_random_network(live)
     w = gx.network_words(net)
     slots = slots or W.LARGE_TABLE_SLOTS
+    if not B or not G:
+        tb, tg, _ = gx.autotune(w, 0.3)
+        B, G = B or tb, G or tg
     torch.cuda.empty_cache()
     t = gx.Table(w, B, slots, subgroup=G, keys_per_subgroup=U, max_hashes=16)
     t0 = time.perf_counter()
@@ -266,7 +270,7 @@ def run_explore_leg(gx, torch, W, live=8, B=32, G=8, U=1, slots=None):
     return {"workload": (f"random network: 12 processes x 64 declared states ({live} live), "
                          f"out-degree 3, 32 labels, 25% rendezvous, seed 1, sink 0.15; "
                          f"{w}-word vectors; table {info.n_slots} slots ({info.bytes / 1e9:.0f} GB), "
-                         f"buckets of {B} words, subgroup {G}, {U} key(s) in flight"),
+                         f"buckets of {B} words and subgroup {G} (autotuned), {U} key(s) in flight"),
             "states": r.n_states, "transitions": r.n_transitions, "levels": len(r.levels),
             "seconds": round(dt, 4), "cold_seconds": round(cold, 4),
             "states_per_s": round(r.n_states / dt),

@@ -278,9 +278,13 @@ __device__ inline Eval evaluate(const uint32_t (&v)[Geo<S, B, G>::K], const uint
   return ev;
 }
 
-// Per-lane statistics, reduced once per wavefront at kernel end.
+// Statistics of a wavefront's find-or-puts.  The per-key outcomes (stored,
+// lookups, full, invalid) are counted once per call with ballots, so they are
+// wavefront-uniform and live in scalar registers; bucket reads and the
+// longest hash chain are per lane (subgroup leaders), reduced at the end.
 struct LaneStats {
-  uint32_t stored = 0, lookups = 0, probes = 0, full = 0, invalid = 0, max_j = 0;
+  uint32_t stored = 0, lookups = 0, full = 0, invalid = 0;  // wavefront totals
+  uint32_t probes = 0, max_j = 0;                            // per lane
 };
 
 __device__ inline uint32_t wave_sum(uint32_t x) {
@@ -299,11 +303,8 @@ __device__ inline uint32_t wave_max(uint32_t x) {
 }
 
 __device__ inline void flush_stats(const TableDev& t, const LaneStats& st, uint64_t* n_new) {
-  const uint32_t stored = wave_sum(st.stored);
-  const uint32_t lookups = wave_sum(st.lookups);
+  const uint32_t stored = st.stored, lookups = st.lookups, full = st.full, invalid = st.invalid;
   const uint32_t probes = wave_sum(st.probes);
-  const uint32_t full = wave_sum(st.full);
-  const uint32_t invalid = wave_sum(st.invalid);
   const uint32_t mj = wave_max(st.max_j);
   if (__lane_id() == 0) {
     if (stored) {
@@ -404,7 +405,6 @@ __device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S
         if (j[u] >= t.H) {
           res[u] = kFull;
           act[u] = false;
-          if (li == 0) ++st.full;
         } else {
           const uint64_t a = t.hc[2 * j[u]], c = t.hc[2 * j[u] + 1];
           bkt[u] = bucket_of(mix[u], a, c, t.n_buckets);
@@ -462,7 +462,6 @@ __device__ inline void find_or_put(const TableDev& t, const uint32_t (&key)[U][S
       if (W) {
         res[u] = kNew;
         act[u] = false;
-        if (li == 0) ++st.stored;
       } else if (Sm) {
         res[u] = kSeen;
         act[u] = false;
@@ -514,9 +513,7 @@ __device__ inline uint8_t find_or_put_lanes(const TableDev& t, const uint32_t (&
   if (own_act && bad) {
     own_res = kInvalid;
     own_act = false;
-    ++st.invalid;
   }
-  if (own_act) ++st.lookups;
   const uint64_t own_mix = key_mix<S>(own, t.seed);
   const uint64_t own_bkt = bucket_of(own_mix, t.a0, t.c0, t.n_buckets);
 #pragma unroll 1
@@ -541,6 +538,10 @@ __device__ inline uint8_t find_or_put_lanes(const TableDev& t, const uint32_t (&
     for (int u = 0; u < U; ++u)
       if (li == c + u && own_act) own_res = res[u];
   }
+  st.lookups += static_cast<uint32_t>(__popcll(__ballot(own_act)));
+  st.invalid += static_cast<uint32_t>(__popcll(__ballot(own_res == kInvalid)));
+  st.stored += static_cast<uint32_t>(__popcll(__ballot(own_res == kNew)));
+  st.full += static_cast<uint32_t>(__popcll(__ballot(own_res == kFull)));
   return own_res;
 }
 
