@@ -334,8 +334,9 @@ gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_op
  * measured find-or-put rate on this device for keys of words_per_state words
  * at the given final load factor (0 < load_factor <= 0.95).  The first call
  * for a (slot words, load) pair times every candidate (B in 8..64, subgroup 8
- * or 16, 1 or 2 keys per subgroup) on a synthetic stream of 2^21 keys; later
- * calls return the cached choice.  Synchronous.
+ * or 16, 1 or 2 keys per subgroup) on a synthetic stream of 2^24 keys, the
+ * fastest of three runs each; later calls return the cached choice.
+ * Synchronous.
  */
 gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bucket_words,
                       uint32_t* subgroup, uint32_t* keys_per_subgroup);

@@ -213,9 +213,11 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
   std::lock_guard<std::mutex> lock(gx::g_tune_mutex);
   auto it = gx::g_tuned.find(key);
   if (it == gx::g_tuned.end()) {
-    // measure every candidate on a synthetic stream: 2^21 keys, each distinct
+    // measure every candidate on a synthetic stream: 2^24 keys, each distinct
     // key about twice, into a table sized for the requested load factor
-    const uint64_t n = 1u << 21, n_distinct = n / 2;
+    // 2^24 keys: the table (64-256 MB) outgrows the L2 and most of the
+    // last-level cache, as the tables it is tuned for do
+    const uint64_t n = 1u << 24, n_distinct = n / 2;
     uint32_t* keys = nullptr;
     uint8_t* status = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -243,16 +245,22 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
             st = GX_ENOMEM;
             continue;
           }
-          float ms = 0;
-          // warm-up, then the timed insertion into the cleared table
+          // warm-up, then the fastest of three timed insertions into the
+          // cleared table
           (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
-          (void)gx_table_clear(t, nullptr);
-          (void)hipEventRecord(e0, nullptr);
-          (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
-          (void)hipEventRecord(e1, nullptr);
-          if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
-              ms < best) {
-            best = ms;
+          float fastest = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            float ms = 0;
+            (void)gx_table_clear(t, nullptr);
+            (void)hipEventRecord(e0, nullptr);
+            (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
+            (void)hipEventRecord(e1, nullptr);
+            if (hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+              fastest = std::min(fastest, ms);
+          }
+          if (fastest < best) {
+            best = fastest;
             pick = {B, G, U};
           }
           gx_table_destroy(t);
@@ -343,6 +351,13 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
     b->classes[k].members.push_back(i);
     b->cls[i] = k;
   }
+  // Largest declared capacity first: the initial queue holds the instances
+  // in member order, so the explorations with the longest chain of levels
+  // start first and the small ones fill the device around them.
+  for (auto& c : b->classes)
+    std::stable_sort(c.members.begin(), c.members.end(), [&](uint32_t x, uint32_t y) {
+      return opts->capacity[x] > opts->capacity[y];
+    });
   // shared hash constants
   std::vector<uint64_t> hc(2 * b->H);
   for (uint32_t j = 0; j < b->H; ++j) gx::hash_constants(b->seed, j, &hc[2 * j], &hc[2 * j + 1]);
