@@ -605,8 +605,10 @@ def main():
     if args.sweep:
         for alpha, H in ((0.5, 8), (0.9, 128)):
             for B in (8, 16, 32, 64):
-                for G in (8, 16, 32, 64):
+                for G in (4, 8, 16, 32, 64):
                     for U in (1, 2, 4, 8):
+                        if U > G or (G == 4 and B > 32):
+                            continue
                         r = run_fop(gx, torch, keys, n_distinct, B, G, U, alpha, H, 2, 1)
                         bpo = algorithmic_bytes_per_op(2, B, r["probes_per_op"], 0.5)
                         r["Mops_per_s"] = n / r["fop_ms"] / 1e3

@@ -55,11 +55,13 @@ typedef struct gx_table gx_table;
 typedef struct {
   uint64_t hash_seed;  /* seed of the hash-constant sets; 0 picks a fixed default */
   uint32_t max_hashes; /* H, hash functions tried before a key is FULL; 0 -> 8      */
-  uint32_t subgroup;   /* lanes that probe one bucket: 8, 16, 32 or 64 (lanes
-                          beyond bucket_words stay idle); 0 -> the larger of 8
-                          and the smaller of bucket_words and 64               */
-  uint32_t keys_per_subgroup; /* keys a subgroup keeps in flight: 1, 2, 4 or 8;
-                                 0 -> 1                                          */
+  uint32_t subgroup;   /* lanes that probe one bucket: 4, 8, 16, 32 or 64
+                          (lanes beyond bucket_words stay idle; a lane holds
+                          at most 8 bucket words, so 4 needs bucket_words <=
+                          32); 0 -> the larger of 8 and the smaller of
+                          bucket_words and 64                                  */
+  uint32_t keys_per_subgroup; /* keys a subgroup keeps in flight: 1, 2, 4 or 8,
+                                 at most subgroup; 0 -> 1                        */
   uint32_t reserved;
 } gx_table_opts;
 

@@ -137,7 +137,8 @@ template <int S, int B, int G>
 struct Geo {
   static_assert(S == 1 || S == 2 || S == 4, "slot words");
   static_assert(B == 4 || B == 8 || B == 16 || B == 32 || B == 64, "bucket words");
-  static_assert(G == 8 || G == 16 || G == 32 || G == 64, "subgroup width");
+  static_assert(G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "subgroup width");
+  static_assert(B / (G < B ? G : B) <= 8, "at most 8 bucket words per lane");
   static constexpr int GE = G < B ? G : B;          // lanes holding bucket words
   static constexpr int K = B / GE;                  // words per lane
   static constexpr int L = K >= S ? 1 : S / K;      // lanes per slot

@@ -693,7 +693,9 @@ hipError_t append_u(uint32_t U, const AppendArgs& a, uint32_t cus, hipStream_t s
     case 1: return launch_append<S, B, G, 1>(a, cus, s);
     case 2: return launch_append<S, B, G, 2>(a, cus, s);
     case 4: return launch_append<S, B, G, 4>(a, cus, s);
-    case 8: return launch_append<S, B, G, 8>(a, cus, s);
+    case 8:
+      if constexpr (G >= 8) return launch_append<S, B, G, 8>(a, cus, s);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -701,6 +703,9 @@ hipError_t append_u(uint32_t U, const AppendArgs& a, uint32_t cus, hipStream_t s
 template <int S, int B>
 hipError_t append_g(uint32_t G, uint32_t U, const AppendArgs& a, uint32_t cus, hipStream_t s) {
   switch (G) {
+    case 4:
+      if constexpr (B <= 32) return append_u<S, B, 4>(U, a, cus, s);
+      break;
     case 8: return append_u<S, B, 8>(U, a, cus, s);
     case 16: return append_u<S, B, 16>(U, a, cus, s);
     case 32: return append_u<S, B, 32>(U, a, cus, s);

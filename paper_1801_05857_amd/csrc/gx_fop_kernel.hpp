@@ -86,7 +86,9 @@ hipError_t dispatch_u(uint32_t U, const FopArgs& a) {
     case 1: return launch_fop<S, B, G, 1>(a);
     case 2: return launch_fop<S, B, G, 2>(a);
     case 4: return launch_fop<S, B, G, 4>(a);
-    case 8: return launch_fop<S, B, G, 8>(a);
+    case 8:
+      if constexpr (G >= 8) return launch_fop<S, B, G, 8>(a);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -94,6 +96,9 @@ hipError_t dispatch_u(uint32_t U, const FopArgs& a) {
 template <int S, int B>
 hipError_t dispatch_g(uint32_t G, uint32_t U, const FopArgs& a) {
   switch (G) {
+    case 4:
+      if constexpr (B <= 32) return dispatch_u<S, B, 4>(U, a);
+      break;
     case 8: return dispatch_u<S, B, 8>(U, a);
     case 16: return dispatch_u<S, B, 16>(U, a);
     case 32: return dispatch_u<S, B, 32>(U, a);

@@ -151,7 +151,8 @@ gx_status gx_table_create(uint32_t w, uint32_t B, uint64_t capacity, const gx_ta
   uint32_t U = opts && opts->keys_per_subgroup ? opts->keys_per_subgroup : 1;
   uint32_t H = opts && opts->max_hashes ? opts->max_hashes : 8;
   uint64_t seed = opts && opts->hash_seed ? opts->hash_seed : 0x1801058570ull;
-  if (!gx::pow2_in(G, 8, 64) || !gx::pow2_in(U, 1, 8) || H > 4096) return GX_EINVAL;
+  if (!gx::pow2_in(G, 4, 64) || !gx::pow2_in(U, 1, 8) || U > G || H > 4096) return GX_EINVAL;
+  if (B / std::min(G, B) > 8) return GX_EINVAL;  // at most 8 bucket words per lane
   const uint64_t slots_per_bucket = B / S;
   const uint64_t n_buckets = (capacity + slots_per_bucket - 1) / slots_per_bucket;
   if (n_buckets > (uint64_t(1) << 40)) return GX_EINVAL;

@@ -48,7 +48,7 @@ def test_status_strings(lib):
 
 @pytest.mark.parametrize("w,B,cap,sub,kps", [
     (0, 32, 10, 0, 0), (5, 32, 10, 0, 0), (1, 12, 10, 0, 0), (1, 2, 10, 0, 0),
-    (1, 128, 10, 0, 0), (2, 32, 0, 0, 0), (2, 32, 10, 12, 0), (2, 32, 10, 4, 0),
+    (1, 128, 10, 0, 0), (2, 32, 0, 0, 0), (2, 32, 10, 12, 0), (2, 64, 10, 4, 0), (2, 32, 10, 2, 0), (2, 32, 10, 4, 8),
     (2, 32, 10, 128, 0), (2, 32, 10, 0, 3), (2, 32, 10, 0, 16)])
 def test_table_create_rejects_bad_arguments(lib, w, B, cap, sub, kps):
     opts = gx._TableOpts(0, 0, sub, kps, 0)

@@ -64,6 +64,7 @@ def test_independent_cycles(dev, sizes):
 
 
 SPECS = [(B, G) for B in (4, 8, 16, 32, 64) for G in (8, 16, 32, 64)]
+SPECS += [(B, 4) for B in (4, 8, 16, 32)]  # 4-lane subgroups
 
 
 def _net_for_words(w):

@@ -79,6 +79,8 @@ def _placement_ok(table, keys_sorted):
 
 GRID = [(w, B, G, U) for w in (1, 2, 3, 4) for B in (4, 8, 16, 32, 64) for G in (8, 16, 32, 64)
         for U in (1, 2, 4, 8)]
+# 4-lane subgroups: buckets of at most 32 words (8 per lane), U <= 4
+GRID += [(w, B, 4, U) for w in (1, 2, 3, 4) for B in (4, 8, 16, 32) for U in (1, 2, 4)]
 
 
 @pytest.mark.parametrize("w,B,G,U", GRID, ids=[f"w{w}-B{B}-G{G}-U{U}" for w, B, G, U in GRID])
