@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--log2n", type=int, default=28, help="log2 of the number of keys")
     ap.add_argument("--bucket", type=int, default=32)
-    ap.add_argument("--subgroup", type=int, default=8)
+    ap.add_argument("--subgroup", type=int, default=4)
     ap.add_argument("--kps", type=int, default=1, help="keys in flight per subgroup")
     ap.add_argument("--alpha", type=float, default=0.5)
     ap.add_argument("--hashes", type=int, default=0)
@@ -135,7 +135,8 @@ def measured_traffic(args):
     (otherwise None)."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "fop_kernel_2p28_B32_G8_U1_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"fop_kernel_2p{args.log2n}_B{args.bucket}_G{args.subgroup}"
+                                          f"_U{args.kps}_traffic.json")
     try:
         meta = json.load(open(path))
     except (OSError, ValueError):
@@ -294,7 +295,8 @@ def run_dup_sweep(gx, torch, W, log2n=27, alpha=0.5):
     rows = []
     for dup in (1, 2, 4, 8, 16, 32, 64):
         keys, _ = W.duplicated_stream_torch(n // dup, dup, SEED, "cuda", w=1)
-        for B, G, U in ((32, 32, 1), (4, 8, 2), (8, 8, 2), (16, 8, 2), (32, 8, 1)):
+        for B, G, U in ((32, 32, 1), (4, 8, 2), (8, 8, 2), (16, 8, 2), (32, 8, 1), (16, 4, 1),
+                        (32, 4, 1)):
             t = gx.Table(1, B, int((n // dup) / alpha) + 1, subgroup=G, keys_per_subgroup=U,
                          max_hashes=32)
             st = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -435,8 +437,10 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
         # reference
         tables = {}
         for nt, sz in pool:
-            tables[id(nt)] = gx.Table(gx.network_words(nt), 32, max(64, int(sz * 2.5)),
-                                      subgroup=8, keys_per_subgroup=1, max_hashes=16)
+            w = gx.network_words(nt)
+            tb, tg, _ = gx.autotune(w, 0.5)  # the server's kernel configuration
+            tables[id(nt)] = gx.Table(w, tb, max(64, int(sz * 2.5)), subgroup=tg,
+                                      keys_per_subgroup=1, max_hashes=16)
             gx.explore(nt, tables[id(nt)])  # sizes its resident buffers
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -294,7 +294,9 @@ typedef struct {
   uint64_t hash_seed;         /* 0 -> the default seed                         */
   uint32_t max_hashes;        /* H; 0 -> 8                                     */
   uint32_t bucket_words;      /* 0 -> autotuned per instance, else 8|16|32|64 */
-  uint32_t subgroup;          /* 0 -> autotuned per instance, else 8|16        */
+  uint32_t subgroup;          /* 0 -> autotuned per instance, else 4|8|16
+                                 (4 with buckets of at most 32 words; an
+                                 explicit 4 caps an autotuned bucket at 32)   */
   uint32_t keys_per_subgroup; /* 0 -> 1, else 1|2                             */
   uint32_t use_graph;         /* nonzero: gx_batch_create captures a whole run
                                  (clears, resets and every launch) in a hipGraph
@@ -335,9 +337,10 @@ gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_op
  * Autotuner: the (bucket words, subgroup, keys per subgroup) with the highest
  * measured find-or-put rate on this device for keys of words_per_state words
  * at the given final load factor (0 < load_factor <= 0.95).  The first call
- * for a (slot words, load) pair times every candidate (B in 8..64, subgroup 8
- * or 16, 1 or 2 keys per subgroup) on a synthetic stream of 2^24 keys, the
- * fastest of three runs each; later calls return the cached choice.
+ * for a (slot words, load) pair times every candidate (B in 8..64, subgroup 4
+ * (B <= 32), 8 or 16, 1 or 2 keys per subgroup) on a synthetic stream of
+ * 2^24 keys, the fastest of three runs each; later calls return the cached
+ * choice.
  * Synchronous.
  */
 gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bucket_words,
@@ -367,7 +370,8 @@ typedef struct {
   double load_factor;         /* table load at the declared bound; 0 -> 0.5   */
   uint64_t hash_seed;         /* 0 -> the default seed                         */
   uint32_t bucket_words;      /* 0 -> autotuned per slot width, else 8..64     */
-  uint32_t subgroup;          /* 0 -> autotuned, else 8|16                     */
+  uint32_t subgroup;          /* 0 -> autotuned, else 4|8|16 (4 with buckets
+                                 of at most 32 words)                         */
   uint32_t keys_per_subgroup; /* 0 -> 1, else 1|2                             */
   uint32_t reserved;
 } gx_server_opts;

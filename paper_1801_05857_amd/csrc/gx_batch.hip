@@ -236,7 +236,8 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
     gx_status st = GX_OK;
     for (uint32_t B : {8u, 16u, 32u, 64u}) {
       if (B < S * 2) continue;
-      for (uint32_t G : {8u, 16u}) {
+      for (uint32_t G : {4u, 8u, 16u}) {
+        if (G == 4 && B > 32) continue;
         for (uint32_t U : {1u, 2u}) {
           gx_table_opts o{0, 64, G, U, 0};
           gx_table* t = nullptr;
@@ -284,7 +285,9 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
                           gx_batch** out) {
   if (!nets || n == 0 || !opts || !opts->capacity || !out) return GX_EINVAL;
   if (opts->bucket_words && !gx::valid_pow2(opts->bucket_words, 8, 64)) return GX_EINVAL;
-  if (opts->subgroup && !(opts->subgroup == 8 || opts->subgroup == 16)) return GX_EINVAL;
+  if (opts->subgroup && !(opts->subgroup == 4 || opts->subgroup == 8 || opts->subgroup == 16))
+    return GX_EINVAL;
+  if (opts->subgroup == 4 && opts->bucket_words > 32) return GX_EINVAL;
   if (opts->keys_per_subgroup && !(opts->keys_per_subgroup == 1 || opts->keys_per_subgroup == 2))
     return GX_EINVAL;
   // compile every network on the host first: argument errors before device work
@@ -329,6 +332,7 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
       // exploration kernels they cost a wave per SIMD of occupancy
       (void)tu;
       U = U ? U : 1;
+      gx::fit_subgroup(&B, &G, opts->bucket_words != 0);
     }
     const uint32_t S = gx::slot_words(words[i]);
     if (B < 2 * S) B = 2 * S;

@@ -275,7 +275,9 @@ hipError_t batch_launch(uint32_t B, uint32_t G, uint32_t U, const BatchArgs& a, 
 #define GX_BATCH_CASE(BB, GG, UU) \
   if (B == BB && G == GG && U == UU) return BatchKernels<S, BB, GG, UU>::launch(a, grid, lds, s);
 #define GX_BATCH_B(BB) GX_BATCH_CASE(BB, 8, 1) GX_BATCH_CASE(BB, 8, 2) GX_BATCH_CASE(BB, 16, 1) GX_BATCH_CASE(BB, 16, 2)
-  GX_BATCH_B(8) GX_BATCH_B(16) GX_BATCH_B(32) GX_BATCH_B(64)
+#define GX_BATCH_B4(BB) GX_BATCH_B(BB) GX_BATCH_CASE(BB, 4, 1) GX_BATCH_CASE(BB, 4, 2)
+  GX_BATCH_B4(8) GX_BATCH_B4(16) GX_BATCH_B4(32) GX_BATCH_B(64)
+#undef GX_BATCH_B4
 #undef GX_BATCH_B
 #undef GX_BATCH_CASE
   return hipErrorInvalidValue;
@@ -286,7 +288,9 @@ int batch_resident(uint32_t B, uint32_t G, uint32_t U, size_t lds) {
 #define GX_BATCH_CASE(BB, GG, UU) \
   if (B == BB && G == GG && U == UU) return BatchKernels<S, BB, GG, UU>::resident_per_cu(lds);
 #define GX_BATCH_B(BB) GX_BATCH_CASE(BB, 8, 1) GX_BATCH_CASE(BB, 8, 2) GX_BATCH_CASE(BB, 16, 1) GX_BATCH_CASE(BB, 16, 2)
-  GX_BATCH_B(8) GX_BATCH_B(16) GX_BATCH_B(32) GX_BATCH_B(64)
+#define GX_BATCH_B4(BB) GX_BATCH_B(BB) GX_BATCH_CASE(BB, 4, 1) GX_BATCH_CASE(BB, 4, 2)
+  GX_BATCH_B4(8) GX_BATCH_B4(16) GX_BATCH_B4(32) GX_BATCH_B(64)
+#undef GX_BATCH_B4
 #undef GX_BATCH_B
 #undef GX_BATCH_CASE
   return 1;

@@ -58,6 +58,17 @@ namespace gx {
 
 inline uint32_t slot_words(uint32_t w) { return w == 3 ? 4u : w; }
 
+// A 4-lane subgroup holds at most 8 words of a bucket per lane, so it pairs
+// with buckets of up to 32 words.  An autotuned value gives way to an
+// explicit one: an explicit 4-lane subgroup caps an autotuned bucket at 32
+// words, an explicit 64-word bucket turns an autotuned 4-lane subgroup into 8.
+inline void fit_subgroup(uint32_t* B, uint32_t* G, bool B_given) {
+  if (*G == 4 && *B > 32) {
+    if (B_given) *G = 8;
+    else *B = 32;
+  }
+}
+
 struct FopArgs {
   TableDev t;
   const uint32_t* keys;

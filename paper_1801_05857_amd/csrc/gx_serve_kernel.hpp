@@ -76,7 +76,9 @@ hipError_t serve_launch(uint32_t B, uint32_t G, uint32_t U, const ServeArgs& a, 
     return hipGetLastError();                                                                  \
   }
 #define GX_SERVE_B(BB) GX_SERVE_CASE(BB, 8, 1) GX_SERVE_CASE(BB, 8, 2) GX_SERVE_CASE(BB, 16, 1) GX_SERVE_CASE(BB, 16, 2)
-  GX_SERVE_B(8) GX_SERVE_B(16) GX_SERVE_B(32) GX_SERVE_B(64)
+#define GX_SERVE_B4(BB) GX_SERVE_B(BB) GX_SERVE_CASE(BB, 4, 1) GX_SERVE_CASE(BB, 4, 2)
+  GX_SERVE_B4(8) GX_SERVE_B4(16) GX_SERVE_B4(32) GX_SERVE_B(64)
+#undef GX_SERVE_B4
 #undef GX_SERVE_B
 #undef GX_SERVE_CASE
   return hipErrorInvalidValue;

@@ -448,7 +448,9 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
   if (opts->bucket_words && !(opts->bucket_words == 8 || opts->bucket_words == 16 ||
                               opts->bucket_words == 32 || opts->bucket_words == 64))
     return GX_EINVAL;
-  if (opts->subgroup && !(opts->subgroup == 8 || opts->subgroup == 16)) return GX_EINVAL;
+  if (opts->subgroup && !(opts->subgroup == 4 || opts->subgroup == 8 || opts->subgroup == 16))
+    return GX_EINVAL;
+  if (opts->subgroup == 4 && opts->bucket_words > 32) return GX_EINVAL;
   if (opts->keys_per_subgroup && !(opts->keys_per_subgroup == 1 || opts->keys_per_subgroup == 2))
     return GX_EINVAL;
   gx_server* s = new (std::nothrow) gx_server;
@@ -478,6 +480,7 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
       // exploration kernels they cost a wave per SIMD of occupancy
       (void)tu;
       U = U ? U : 1;
+      gx::fit_subgroup(&B, &G, opts->bucket_words != 0);
     }
     if (B < 2 * S) B = 2 * S;
     s->cfg[S][0] = B;

@@ -170,6 +170,11 @@ def test_batch_arguments_rejected_before_device_work(lib):
     assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
     opts = gx._BatchOpts(cap.ctypes.data, 0, 0, 0, 32, 0, 0, 0, 0, None)
     assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    # a 4-lane subgroup covers at most 32 bucket words
+    opts = gx._BatchOpts(cap.ctypes.data, 0, 0, 64, 4, 0, 0, 0, 0, None)
+    assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._BatchOpts(cap.ctypes.data, 0, 0, 0, 2, 0, 0, 0, 0, None)
+    assert lib.gx_batch_create(arr, 1, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
     assert lib.gx_batch_create(arr, 0, ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
     assert not out.value
     assert lib.gx_batch_run(None, None) == gx.GX_EINVAL
@@ -187,6 +192,10 @@ def test_server_arguments_rejected(lib):
     opts = gx._ServerOpts(1 << 20, 0, 0, 0.99, 0, 0, 0, 0, 0)
     assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
     opts = gx._ServerOpts(1 << 20, 0, 0, 0.5, 0, 12, 0, 0, 0)
+    assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._ServerOpts(1 << 20, 0, 0, 0.5, 0, 64, 4, 0, 0)
+    assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
+    opts = gx._ServerOpts(1 << 20, 0, 0, 0.5, 0, 0, 32, 0, 0)
     assert lib.gx_server_create(ctypes.byref(opts), ctypes.byref(out)) == gx.GX_EINVAL
     assert not out.value
     rid = ctypes.c_uint64()

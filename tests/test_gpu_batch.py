@@ -64,13 +64,25 @@ def test_batch_matches_oracle(dev, mixed, use_graph):
         _check(b.results(), want)
 
 
-@pytest.mark.parametrize("B,G,U", [(8, 8, 1), (16, 16, 2), (64, 8, 2), (32, 16, 1)])
+@pytest.mark.parametrize("B,G,U", [(8, 8, 1), (16, 16, 2), (64, 8, 2), (32, 16, 1),
+                                   (8, 4, 2), (16, 4, 1), (32, 4, 2)])
 def test_batch_explicit_configurations(dev, mixed, B, G, U):
     nets, want = mixed
     cap = [max(64, 4 * r.n_states) for r in want]
     res = gx.explore_batch(nets, cap, bucket_words=B, subgroup=G, keys_per_subgroup=U,
                            max_hashes=64)
     _check(res, want)
+
+
+def test_explicit_subgroup_of_four_caps_autotuned_bucket(dev, mixed):
+    nets, want = mixed
+    cap = [max(64, 4 * r.n_states) for r in want]
+    with gx.Batch(nets, cap, subgroup=4, max_hashes=64) as b:
+        for i in range(len(nets)):
+            B, G, U = b.instance_config(i)
+            assert G == 4 and B <= 32 and U == 1
+        b.run()
+        _check(b.results(), want)
 
 
 def test_batch_equals_single_explorations(dev, mixed):

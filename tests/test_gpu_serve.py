@@ -65,6 +65,18 @@ def test_served_mix_equals_oracle(dev, reqs):
         assert s["active_peak"] > 1  # requests really overlapped on the device
 
 
+@pytest.mark.parametrize("B,G,U", [(16, 4, 1), (32, 4, 2), (64, 16, 2)])
+def test_served_mix_explicit_configurations(dev, reqs, B, G, U):
+    nets, want = reqs
+    with gx.Server(8 << 30, max_hashes=32, bucket_words=B, subgroup=G,
+                   keys_per_subgroup=U) as srv:
+        ids = [srv.submit(n, max(16, 2 * r.n_states)) for n, r in zip(nets, want)]
+        for rid, ref in zip(ids, want):
+            st, got, _ = srv.poll(rid)
+            assert st == gx.GX_OK
+            _same(got, ref)
+
+
 def test_small_budget_queues_and_still_serves_all(dev, reqs):
     nets, want = reqs
     # room for only a few requests at a time (the largest reservation, the
