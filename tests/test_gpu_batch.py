@@ -120,5 +120,6 @@ def test_batch_of_many_small_instances(dev):
 def test_autotune_returns_a_valid_configuration(dev):
     for w in (1, 2, 3):
         B, G, U = gx.autotune(w, 0.5)
-        assert B in (8, 16, 32, 64) and G in (8, 16) and U in (1, 2)
+        assert B in (8, 16, 32, 64) and G in (4, 8, 16) and U in (1, 2)
+        assert G != 4 or B <= 32  # a 4-lane subgroup covers at most 32 words
         assert gx.autotune(w, 0.5) == (B, G, U)  # cached
