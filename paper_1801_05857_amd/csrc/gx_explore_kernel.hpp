@@ -160,31 +160,42 @@ __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) 
   }
 }
 
-// Write every successor of this state (the successors emit_successors
-// numbers, not necessarily in its order) to out[k * S] (global memory; one
-// lane writes a contiguous run).
+// Write every successor of the wavefront's states to out[k * S], k < total
+// (global memory), with coalesced stores.  The lanes walk their transitions
+// in step: every loop runs until no lane has work left in it (its exit test
+// is a ballot, so the wavefront never splits), and at each step the lanes
+// that form a successor write it to consecutive slots after those the
+// wavefront has filled so far.  One store instruction thus covers a
+// contiguous run of slots, where a run per lane would touch a cache line per
+// lane.  Must be reached by the whole wavefront; a lane without a state
+// passes has = false.
 template <int S>
-__device__ __forceinline__ void emit_all(const uint32_t* img, const uint32_t (&sw)[S],
-                                         uint32_t* out) {
+__device__ __forceinline__ void emit_coalesced(const uint32_t* img, const uint32_t (&sw)[S],
+                                               bool has, uint32_t* out, uint32_t total) {
   const uint32_t P = img[0], R = img[1];
-  uint32_t* o = out;
-  // Targets are read from LDS four at a time before any successor of the
-  // group is formed, so one LDS round trip serves up to four successors.
-  auto emit_range = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t s1) {
-    for (uint32_t t = s0; t < s1; t += 4) {
+  uint32_t cur = 0;  // slots the wavefront has filled (the same in every lane)
+  auto put = [&](bool act, const uint32_t (&succ)[S]) {
+    const uint64_t m = __ballot(act);
+    const uint32_t r = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+    if (act && cur + r < total) store_slot<S>(out + static_cast<uint64_t>(cur + r) * S, succ);
+    cur += static_cast<uint32_t>(__popcll(m));
+  };
+  // successors: `from` with field f set to each of img[s0 .. s0 + n); targets
+  // are read from LDS four at a time before any successor of the group is
+  // formed, so one LDS round trip serves up to four successors
+  auto run = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t n) {
+    for (uint32_t t = 0; __ballot(t < n); t += 4) {
       uint32_t d[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) d[k] = img[min(t + k, s1 - 1)];
+      for (int k = 0; k < 4; ++k) d[k] = t + k < n ? img[s0 + t + k] : 0u;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (t + k < s1) {
-          uint32_t succ[S];
+        uint32_t succ[S];
 #pragma unroll
-          for (int x = 0; x < S; ++x) succ[x] = from[x];
-          set_field<S>(succ, f, d[k]);
-          store_slot<S>(o, succ);
-          o += S;
-        }
+        for (int x = 0; x < S; ++x) succ[x] = from[x];
+        set_field<S>(succ, f, d[k]);
+        put(t + k < n, succ);
       }
     }
   };
@@ -192,7 +203,8 @@ __device__ __forceinline__ void emit_all(const uint32_t* img, const uint32_t (&s
     const uint32_t f = img[4 + p];
     const uint32_t l = get_field<S>(sw, f);
     const uint32_t ob = img[4 + P + p];
-    emit_range(sw, f, img[ob + l], img[ob + l + 1]);
+    const uint32_t s0 = img[ob + l];
+    run(sw, f, s0, has ? img[ob + l + 1] - s0 : 0u);
   }
   for (uint32_t r = 0; r < R; ++r) {
     const uint32_t rb = img[4 + 2 * P + r];
@@ -204,38 +216,41 @@ __device__ __forceinline__ void emit_all(const uint32_t* img, const uint32_t (&s
       const uint32_t f1 = img[4 + img[rb + 3]], ob1 = img[rb + 4];
       const uint32_t l0 = get_field<S>(sw, f0), l1 = get_field<S>(sw, f1);
       const uint32_t a0 = img[ob0 + l0], e0 = img[ob0 + l0 + 1];
-      const uint32_t a1 = img[ob1 + l1], e1 = img[ob1 + l1 + 1];
-      if (a1 == e1) continue;
-      for (uint32_t t0 = a0; t0 < e0; ++t0) {
+      const uint32_t a1 = img[ob1 + l1], n1 = img[ob1 + l1 + 1] - a1;
+      const uint32_t n0 = has && n1 ? e0 - a0 : 0u;
+      for (uint32_t t0 = 0; __ballot(t0 < n0); ++t0) {
+        const bool act = t0 < n0;
         uint32_t mid[S];
 #pragma unroll
         for (int x = 0; x < S; ++x) mid[x] = sw[x];
-        set_field<S>(mid, f0, img[t0]);
-        emit_range(mid, f1, a1, e1);
+        set_field<S>(mid, f0, act ? img[a0 + t0] : 0u);
+        run(mid, f1, a1, act ? n1 : 0u);
       }
       continue;
     }
-    uint32_t prod = 1;
+    uint32_t prod = has ? 1u : 0u;
     for (uint32_t i = 0; i < np && prod; ++i) {
       const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
       const uint32_t l = get_field<S>(sw, img[4 + q]);
       prod *= img[ob + l + 1] - img[ob + l];
     }
-    for (uint32_t c = 0; c < prod; ++c) {
+    for (uint32_t c = 0; __ballot(c < prod); ++c) {
+      const bool act = c < prod;
       uint32_t succ[S];
 #pragma unroll
       for (int x = 0; x < S; ++x) succ[x] = sw[x];
-      uint32_t rem = c;
-      for (uint32_t i = 0; i < np; ++i) {
-        const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
-        const uint32_t fq = img[4 + q];
-        const uint32_t l = get_field<S>(sw, fq);
-        const uint32_t b0 = img[ob + l], cnt = img[ob + l + 1] - b0;
-        set_field<S>(succ, fq, img[b0 + rem % cnt]);
-        rem /= cnt;
+      if (act) {
+        uint32_t rem = c;
+        for (uint32_t i = 0; i < np; ++i) {
+          const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
+          const uint32_t fq = img[4 + q];
+          const uint32_t l = get_field<S>(sw, fq);
+          const uint32_t b0 = img[ob + l], cnt = img[ob + l + 1] - b0;
+          set_field<S>(succ, fq, img[b0 + rem % cnt]);
+          rem /= cnt;
+        }
       }
-      store_slot<S>(o, succ);
-      o += S;
+      put(act, succ);
     }
   }
 }
@@ -558,13 +573,13 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
     return;
   }
   // No filter: one atomic add per workgroup reserves the room of all its
-  // successors; every lane then writes its own successors, a contiguous run,
-  // in one pass over its transitions.
+  // successors; every wavefront then writes its own with coalesced stores
+  // in one pass over its lanes' transitions.
   const int lane = __lane_id();
   uint32_t sw[S];
   const uint32_t c = gen_count<S>(a, img, first + lane, sw);
   uint32_t total = 0;
-  const uint32_t off = wave_exclusive_scan(c, &total);
+  (void)wave_exclusive_scan(c, &total);
   if (lane == 0) wave_total[wave] = total;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -584,9 +599,9 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   }
   __syncthreads();
   uint64_t base = group_base;
-  if (base == ~0ull || c == 0) return;
+  if (base == ~0ull || total == 0) return;
   for (int w = 0; w < wave; ++w) base += wave_total[w];
-  emit_all<S>(img, sw, a.succ + (base + off) * S);
+  emit_coalesced<S>(img, sw, first + lane < a.n_in, a.succ + base * S, total);
 }
 
 struct AppendArgs {
