@@ -68,70 +68,6 @@ __device__ __forceinline__ uint32_t count_successors(const uint32_t* img, const 
   return c;
 }
 
-// Write successors with ordinals in [lo, hi) of this state to stage[(k-lo)*S].
-template <int S>
-__device__ __forceinline__ void emit_successors(const uint32_t* img, const uint32_t (&sw)[S], int lo,
-                                       int hi, uint32_t* stage) {
-  const uint32_t P = img[0], R = img[1];
-  int k = 0;
-  for (uint32_t p = 0; p < P; ++p) {
-    const uint32_t f = img[4 + p];
-    const uint32_t l = get_field<S>(sw, f);
-    const uint32_t ob = img[4 + P + p];
-    const uint32_t s0 = img[ob + l], s1 = img[ob + l + 1];
-    const int n = static_cast<int>(s1 - s0);
-    if (k + n <= lo) {
-      k += n;
-      continue;
-    }
-    for (uint32_t t = s0; t < s1; ++t, ++k) {
-      if (k >= hi) return;
-      if (k >= lo) {
-        uint32_t succ[S];
-#pragma unroll
-        for (int x = 0; x < S; ++x) succ[x] = sw[x];
-        set_field<S>(succ, f, img[t]);
-#pragma unroll
-        for (int x = 0; x < S; ++x) stage[(k - lo) * S + x] = succ[x];
-      }
-    }
-  }
-  for (uint32_t r = 0; r < R; ++r) {
-    const uint32_t rb = img[4 + 2 * P + r];
-    const uint32_t np = img[rb];
-    uint32_t prod = 1;
-    for (uint32_t i = 0; i < np && prod; ++i) {
-      const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
-      const uint32_t l = get_field<S>(sw, img[4 + q]);
-      prod *= img[ob + l + 1] - img[ob + l];
-    }
-    const int n = static_cast<int>(prod);
-    if (k + n <= lo) {
-      k += n;
-      continue;
-    }
-    for (uint32_t c = 0; c < prod; ++c, ++k) {
-      if (k >= hi) return;
-      if (k >= lo) {
-        uint32_t succ[S];
-#pragma unroll
-        for (int x = 0; x < S; ++x) succ[x] = sw[x];
-        uint32_t rem = c;
-        for (uint32_t i = 0; i < np; ++i) {
-          const uint32_t q = img[rb + 1 + 2 * i], ob = img[rb + 2 + 2 * i];
-          const uint32_t fq = img[4 + q];
-          const uint32_t l = get_field<S>(sw, fq);
-          const uint32_t b0 = img[ob + l], cnt = img[ob + l + 1] - b0;
-          set_field<S>(succ, fq, img[b0 + rem % cnt]);
-          rem /= cnt;
-        }
-#pragma unroll
-        for (int x = 0; x < S; ++x) stage[(k - lo) * S + x] = succ[x];
-      }
-    }
-  }
-}
-
 template <int S>
 __device__ __forceinline__ void load_slot(const uint32_t* p, uint32_t (&k)[S]) {
   if constexpr (S == 4) {
@@ -160,32 +96,49 @@ __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) 
   }
 }
 
-// Write every successor of the wavefront's states to out[k * S], k < total
-// (global memory), with coalesced stores.  The lanes walk their transitions
-// in step: every loop runs until no lane has work left in it (its exit test
-// is a ballot, so the wavefront never splits), and at each step the lanes
-// that form a successor write it to consecutive slots after those the
-// wavefront has filled so far.  One store instruction thus covers a
-// contiguous run of slots, where a run per lane would touch a cache line per
-// lane.  Must be reached by the whole wavefront; a lane without a state
-// passes has = false.
-template <int S>
-__device__ __forceinline__ void emit_coalesced(const uint32_t* img, const uint32_t (&sw)[S],
-                                               bool has, uint32_t* out, uint32_t total) {
+// The wavefront's successors, numbered in the order below, with numbers in
+// [lo, hi) written to out[(k - lo) * S] (global memory or LDS) with
+// coalesced stores.  The lanes walk their transitions in step: every loop
+// runs until no lane has work left in it (its exit test is a ballot, so the
+// wavefront never splits), and at each step the lanes that form a successor
+// take consecutive numbers after those the wavefront has numbered so far.
+// One store instruction thus covers a contiguous run of slots, where a run
+// per lane would touch a cache line per lane.  kWindow: runs whose numbers
+// all lie below lo are counted with one wavefront sum instead of walked, and
+// the walk stops at hi (used to expand a wavefront's successors chunk by
+// chunk); without it the window must be [0, total).  Must be reached by the
+// whole wavefront; a lane without a state passes has = false.
+template <int S, bool kWindow>
+__device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t (&sw)[S],
+                                            bool has, uint32_t* out, uint32_t lo, uint32_t hi) {
   const uint32_t P = img[0], R = img[1];
-  uint32_t cur = 0;  // slots the wavefront has filled (the same in every lane)
+  uint32_t cur = 0;  // successors the wavefront has numbered (the same in every lane)
   auto put = [&](bool act, const uint32_t (&succ)[S]) {
     const uint64_t m = __ballot(act);
-    const uint32_t r = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-    if (act && cur + r < total) store_slot<S>(out + static_cast<uint64_t>(cur + r) * S, succ);
+    const uint32_t k = cur + __builtin_amdgcn_mbcnt_hi(
+                                 static_cast<uint32_t>(m >> 32),
+                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+    if (act && k >= lo && k < hi) store_slot<S>(out + static_cast<uint64_t>(k - lo) * S, succ);
     cur += static_cast<uint32_t>(__popcll(m));
+  };
+  // true when all n successors per lane still to come lie below the window:
+  // then they are only counted
+  auto below = [&](uint32_t n) -> bool {
+    if constexpr (kWindow) {
+      const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_sum(n));
+      if (cur + tot <= lo) {
+        cur += tot;
+        return true;
+      }
+    }
+    return false;
   };
   // successors: `from` with field f set to each of img[s0 .. s0 + n); targets
   // are read from LDS four at a time before any successor of the group is
   // formed, so one LDS round trip serves up to four successors
   auto run = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t n) {
-    for (uint32_t t = 0; __ballot(t < n); t += 4) {
+    if (below(n)) return;
+    for (uint32_t t = 0; cur < hi && __ballot(t < n); t += 4) {
       uint32_t d[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) d[k] = t + k < n ? img[s0 + t + k] : 0u;
@@ -199,14 +152,14 @@ __device__ __forceinline__ void emit_coalesced(const uint32_t* img, const uint32
       }
     }
   };
-  for (uint32_t p = 0; p < P; ++p) {
+  for (uint32_t p = 0; p < P && cur < hi; ++p) {
     const uint32_t f = img[4 + p];
     const uint32_t l = get_field<S>(sw, f);
     const uint32_t ob = img[4 + P + p];
     const uint32_t s0 = img[ob + l];
     run(sw, f, s0, has ? img[ob + l + 1] - s0 : 0u);
   }
-  for (uint32_t r = 0; r < R; ++r) {
+  for (uint32_t r = 0; r < R && cur < hi; ++r) {
     const uint32_t rb = img[4 + 2 * P + r];
     const uint32_t np = img[rb];
     if (np == 2) {
@@ -218,7 +171,8 @@ __device__ __forceinline__ void emit_coalesced(const uint32_t* img, const uint32
       const uint32_t a0 = img[ob0 + l0], e0 = img[ob0 + l0 + 1];
       const uint32_t a1 = img[ob1 + l1], n1 = img[ob1 + l1 + 1] - a1;
       const uint32_t n0 = has && n1 ? e0 - a0 : 0u;
-      for (uint32_t t0 = 0; __ballot(t0 < n0); ++t0) {
+      if (below(n0 * n1)) continue;
+      for (uint32_t t0 = 0; cur < hi && __ballot(t0 < n0); ++t0) {
         const bool act = t0 < n0;
         uint32_t mid[S];
 #pragma unroll
@@ -234,7 +188,8 @@ __device__ __forceinline__ void emit_coalesced(const uint32_t* img, const uint32
       const uint32_t l = get_field<S>(sw, img[4 + q]);
       prod *= img[ob + l + 1] - img[ob + l];
     }
-    for (uint32_t c = 0; __ballot(c < prod); ++c) {
+    if (below(prod)) continue;
+    for (uint32_t c = 0; cur < hi && __ballot(c < prod); ++c) {
       const bool act = c < prod;
       uint32_t succ[S];
 #pragma unroll
@@ -398,19 +353,14 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
   for (uint32_t lo = 0; lo < total; lo += CAP) {
     const uint32_t hi = min(total, lo + CAP);
     {
-      // The state, its successor count and offset are recomputed for every
-      // chunk rather than kept: nothing of the generation stays live in
-      // registers while the chunk is probed, which keeps the probe phase at
-      // the find-or-put kernel's register budget.
+      // The state is reloaded for every chunk rather than kept: nothing of
+      // the generation stays live in registers while the chunk is probed,
+      // which keeps the probe phase at the find-or-put kernel's register
+      // budget.
       uint32_t sw[S];
 #pragma unroll
       for (int x = 0; x < S; ++x) sw[x] = has ? j.frontier_in[i * S + x] : 0u;
-      const uint32_t c = has ? count_successors<S>(j.img, sw) : 0u;
-      uint32_t t2 = 0;
-      const uint32_t off = wave_exclusive_scan(c, &t2);
-      if (c && off < hi && off + c > lo)
-        emit_successors<S>(j.img, sw, static_cast<int>(lo) - static_cast<int>(off),
-                           static_cast<int>(hi) - static_cast<int>(off), stage);
+      emit_window<S, true>(j.img, sw, has, stage, lo, hi);
     }
     wave_lds_sync();
     const uint32_t n_st = hi - lo;
@@ -515,14 +465,13 @@ __device__ inline void gen_wave_filtered(const GenArgs& a, const uint32_t* img, 
   uint32_t sw[S];
   const uint32_t c = gen_count<S>(a, img, first + lane, sw);
   uint32_t total = 0;
-  const uint32_t off = wave_exclusive_scan(c, &total);
+  (void)wave_exclusive_scan(c, &total);
   if (lane == 0 && total)
     atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(total));
+  const bool has = first + lane < a.n_in;
   for (uint32_t lo = 0; lo < total; lo += CAP) {
     const uint32_t hi = min(total, lo + CAP);
-    if (c && off < hi && off + c > lo)
-      emit_successors<S>(img, sw, static_cast<int>(lo) - static_cast<int>(off),
-                         static_cast<int>(hi) - static_cast<int>(off), stage);
+    emit_window<S, true>(img, sw, has, stage, lo, hi);
     wave_lds_sync();
     const uint32_t n_st = hi - lo;
     uint32_t dupmask = 0;
@@ -555,7 +504,9 @@ __device__ inline void gen_wave_filtered(const GenArgs& a, const uint32_t* img, 
   }
 }
 
-template <int S>
+// kFilter (a.dedup set): the chunked path with the duplicate filter, built as
+// its own kernel so its registers do not lower the plain path's occupancy.
+template <int S, bool kFilter>
 __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   extern __shared__ uint32_t smem[];
   __shared__ uint32_t wave_total[4];
@@ -565,7 +516,7 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   __syncthreads();
   const int wave = static_cast<int>(threadIdx.x >> 6);
   const uint64_t first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
-  if (a.dedup) {
+  if constexpr (kFilter) {
     // staging and filter space only with the duplicate filter
     uint32_t* stage = smem + a.img_stride + wave * (kStageWords / 4);
     uint32_t* dtab = smem + a.img_stride + kStageWords + wave * dedup_entries<S>();
@@ -601,7 +552,7 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   uint64_t base = group_base;
   if (base == ~0ull || total == 0) return;
   for (int w = 0; w < wave; ++w) base += wave_total[w];
-  emit_coalesced<S>(img, sw, first + lane < a.n_in, a.succ + base * S, total);
+  emit_window<S, false>(img, sw, first + lane < a.n_in, a.succ + base * S, 0, total);
 }
 
 struct AppendArgs {
@@ -692,13 +643,17 @@ hipError_t launch_append(const AppendArgs& a, uint32_t cus, hipStream_t s) {
 
 template <int S>
 hipError_t launch_gen(const GenArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
+  const void* k = a.dedup ? reinterpret_cast<const void*>(&gen_level_kernel<S, true>)
+                         : reinterpret_cast<const void*>(&gen_level_kernel<S, false>);
   if (lds > 65536) {  // more than the default per-workgroup LDS: ask for it
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gen_level_kernel<S>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                              static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((gen_level_kernel<S>), dim3(grid), dim3(256), lds, s, a);
+  if (a.dedup)
+    hipLaunchKernelGGL((gen_level_kernel<S, true>), dim3(grid), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((gen_level_kernel<S, false>), dim3(grid), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
