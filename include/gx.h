@@ -339,8 +339,9 @@ gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_op
  * at the given final load factor (0 < load_factor <= 0.95).  The first call
  * for a (slot words, load) pair times every candidate (B in 8..64, subgroup 4
  * (B <= 32), 8 or 16, 1 or 2 keys per subgroup) on a synthetic stream of
- * 2^24 keys, the fastest of three runs each; later calls return the cached
- * choice.
+ * 2^26 keys (each distinct key about 8 times), the fastest of three runs
+ * each, and returns the first candidate in that order (smaller buckets
+ * first) within 2% of the fastest; later calls return the cached choice.
  * Synchronous.
  */
 gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bucket_words,

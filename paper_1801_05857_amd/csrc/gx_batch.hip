@@ -11,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "gx_batch_kernel.hpp"
@@ -213,11 +214,13 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
   std::lock_guard<std::mutex> lock(gx::g_tune_mutex);
   auto it = gx::g_tuned.find(key);
   if (it == gx::g_tuned.end()) {
-    // measure every candidate on a synthetic stream: 2^24 keys, each distinct
-    // key about twice, into a table sized for the requested load factor
-    // 2^24 keys: the table (64-256 MB) outgrows the L2 and most of the
-    // last-level cache, as the tables it is tuned for do
-    const uint64_t n = 1u << 24, n_distinct = n / 2;
+    // measure every candidate on a synthetic stream of 2^26 keys, each
+    // distinct key about 8 times (most lookups find their key, as the
+    // successor lookups of an exploration do), into a table sized for the
+    // requested load factor (150-900 MB: beyond the L2 and the last-level
+    // cache, as the tables it is tuned for are); shorter streams end before
+    // the kernel reaches its steady rate
+    const uint64_t n = 1u << 26, n_distinct = n / 8;
     uint32_t* keys = nullptr;
     uint8_t* status = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -232,7 +235,7 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
     hipLaunchKernelGGL(gx::tune_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, nullptr, keys,
                        S, n, n_distinct, 0x5EEDull);
     float best = 1e30f;
-    std::array<uint32_t, 3> pick{32, 8, 1};
+    std::vector<std::pair<float, std::array<uint32_t, 3>>> timed;  // in candidate order
     gx_status st = GX_OK;
     for (uint32_t B : {8u, 16u, 32u, 64u}) {
       if (B < S * 2) continue;
@@ -260,10 +263,8 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
                 hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
               fastest = std::min(fastest, ms);
           }
-          if (fastest < best) {
-            best = fastest;
-            pick = {B, G, U};
-          }
+          best = std::min(best, fastest);
+          timed.push_back({fastest, {B, G, U}});
           gx_table_destroy(t);
         }
       }
@@ -273,6 +274,17 @@ gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best >= 1e30f) return st == GX_OK ? GX_EDEVICE : st;
+    // the first candidate within 2% of the fastest: candidates are ordered by
+    // bucket size, then subgroup, then keys in flight, so near-ties go to the
+    // smaller bucket (fewer bytes per probe; in explorations with 4-word
+    // slots 16-word buckets beat 32-word ones that tie on this stream)
+    std::array<uint32_t, 3> pick{32, 8, 1};
+    for (const auto& c : timed) {
+      if (c.first <= best * 1.02f) {
+        pick = c.second;
+        break;
+      }
+    }
     it = gx::g_tuned.emplace(key, pick).first;
   }
   *B_out = it->second[0];
