@@ -126,17 +126,23 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
     if (threadIdx.x == 0) {
       uint32_t stop = 0;
       uint64_t polls = 0;
+      // Flags and indices are polled with relaxed agent-scope loads; the one
+      // acquire is the load of the entry's ready flag, which orders this
+      // workgroup after the publisher of the level (and, through its own
+      // acquire, after every workgroup that wrote the level's frontier).  An
+      // agent-scope acquire costs an L2 invalidate, a release an L2
+      // write-back.
       while (true) {
-        if (ld_acq(&a.g->abort)) {
+        if (ld_rlx(&a.g->abort)) {
           stop = 1;
           break;
         }
-        if (ld_acq(&a.g->done) >= a.n) {
+        if (ld_rlx(&a.g->done) >= a.n) {
           stop = 1;
           break;
         }
-        const uint32_t h = ld_acq(&a.g->head);
-        const uint32_t tl = ld_acq(&a.g->tail);
+        const uint32_t h = ld_rlx(&a.g->head);
+        const uint32_t tl = ld_rlx(&a.g->tail);
         bool got = false;
         if (h < tl && h < a.queue_cap) {
           BatchEntry* e = &a.queue[h];
@@ -169,9 +175,11 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
       }
       sh_stop = stop;
     }
+    // the barrier orders every wavefront after thread 0's acquire: the
+    // level's frontier and instance state are visible without a fence of
+    // their own
     __syncthreads();
     if (sh_stop) break;
-    __threadfence();  // acquire: the level's frontier and instance state
     const uint32_t iid = uniform32(sh_inst);
     const uint32_t tile = uniform32(sh_tile);
     const BatchInst& in = a.inst[iid];
@@ -200,7 +208,9 @@ __global__ __launch_bounds__(256) void batch_explore_kernel(BatchArgs a) {
     if (j.first < j.n_in) expand_wave<S, B, G, U>(j, stage, st);
     __syncthreads();
     if (threadIdx.x == 0) {
-      __threadfence();  // release this tile's frontier writes
+      // release this tile's frontier writes (an L2 write-back; no
+      // invalidate unless this is the level's last tile)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       BatchEntry* e = &a.queue[sh_entry];
       const uint32_t fin = atomicAdd(&e->finished, 1u) + 1u;
       if (fin == e->tiles) {
