@@ -56,6 +56,9 @@ class _Result(ctypes.Structure):
         ("n_deadlocks", ctypes.c_uint64),
         ("deadlocks", ctypes.POINTER(ctypes.c_uint32)),
         ("visited", ctypes.POINTER(ctypes.c_uint32)),
+        ("n_violations", ctypes.c_uint64),
+        ("violations", ctypes.POINTER(ctypes.c_uint32)),
+        ("violation_level", ctypes.c_uint32),
     ]
 
 
@@ -86,6 +89,9 @@ def _load():
         net_args = [u32, vp, vp, vp, vp, vp, vp, u32, u32, vp]
         lib.oracle_explore.restype = i32
         lib.oracle_explore.argtypes = net_args + [u64, u32, i32, ctypes.POINTER(_Result)]
+        lib.oracle_explore_monitored.restype = i32
+        lib.oracle_explore_monitored.argtypes = net_args + [u64, u32, i32, i32, vp, i32,
+                                                            ctypes.POINTER(_Result)]
         lib.oracle_bruteforce.restype = i32
         lib.oracle_bruteforce.argtypes = net_args + [i32, ctypes.POINTER(_Result)]
         lib.oracle_result_free.argtypes = [ctypes.POINTER(_Result)]
@@ -146,6 +152,8 @@ class OracleResult:
     levels: np.ndarray  # uint64
     deadlocks: np.ndarray  # (n, words) uint32, sorted
     visited: np.ndarray | None  # (n_states, words) uint32, sorted
+    violations: np.ndarray = None  # (n, words) uint32, sorted (safety monitor)
+    violation_level: int | None = None  # first level holding a violation
 
 
 def _flatten(net):
@@ -175,20 +183,40 @@ def _collect(res: _Result, want_visited: bool) -> OracleResult:
     vis = None
     if want_visited:
         vis = np.ctypeslib.as_array(res.visited, shape=(res.n_states * w,)).copy().reshape(-1, w)
+    if res.n_violations:
+        viol = np.ctypeslib.as_array(res.violations, shape=(res.n_violations * w,)).copy()
+    else:
+        viol = np.zeros(0, np.uint32)
+    vl = None if res.violation_level == 0xFFFFFFFF else int(res.violation_level)
     out = OracleResult(w, int(res.n_states), int(res.n_transitions), levels,
-                       dead.reshape(-1, w), vis)
+                       dead.reshape(-1, w), vis, viol.reshape(-1, w), vl)
     _load().oracle_result_free(ctypes.byref(res))
     return out
 
 
 def explore(net, max_states: int = 0, want_visited: bool = False,
-            max_levels: int = 0) -> OracleResult:
+            max_levels: int = 0, monitor=None,
+            stop_on_violation: bool = False) -> OracleResult:
     """Plain BFS of the synchronous product (Sec. 3).  max_levels > 0: stop
-    once levels 0 .. max_levels-1 are known (a BFS prefix)."""
+    once levels 0 .. max_levels-1 are known (a BFS prefix).  monitor =
+    (process, bad) checks a safety property (Sec. 3): a state whose local
+    state of that process is marked in ``bad`` (one flag per local state)
+    violates it; with stop_on_violation the search ends after the first level
+    that holds a violation (counted, not expanded)."""
     args, keep = _flatten(net)
     res = _Result()
-    rc = _load().oracle_explore(*args, max_states, max_levels, int(want_visited),
-                                ctypes.byref(res))
+    if monitor is None:
+        rc = _load().oracle_explore(*args, max_states, max_levels, int(want_visited),
+                                    ctypes.byref(res))
+    else:
+        proc, bad = monitor
+        badv = np.ascontiguousarray(np.asarray(bad).astype(np.uint8))
+        if badv.shape[0] != int(net.n_states[proc]):
+            raise ValueError("one bad flag per local state of the monitor process")
+        rc = _load().oracle_explore_monitored(*args, max_states, max_levels, int(want_visited),
+                                              int(proc), _ptr(badv), int(stop_on_violation),
+                                              ctypes.byref(res))
+        del badv
     del keep
     if rc == -1:
         raise ValueError("invalid network")

@@ -14,6 +14,9 @@
 //   * exploration (Sec. 3, Fig. 1): breadth-first construction of the reachable
 //     part of the synchronous product of a network of LTSs, layer by layer,
 //     with deadlock detection (states without an outgoing product transition).
+//   * safety checking (Sec. 3): the negation of a safety property is an
+//     automaton added to the network as one more process; a reachable state
+//     whose monitor process sits in a bad local state is a violation.
 //   * packing (Sec. 3 and Sec. 5.2): process states are packed into 32-bit
 //     integers; a vector that needs more than one integer spans several words.
 //
@@ -312,6 +315,9 @@ struct oracle_result {
   uint64_t n_deadlocks;
   uint32_t* deadlocks;    // n_deadlocks x words, sorted
   uint32_t* visited;      // n_states x words, sorted (only when requested)
+  uint64_t n_violations;  // reachable states whose monitor process is in a bad state
+  uint32_t* violations;   // n_violations x words, sorted
+  uint32_t violation_level;  // first level holding one; 0xFFFFFFFF when none
 };
 
 void oracle_result_free(oracle_result* r) {
@@ -319,9 +325,22 @@ void oracle_result_free(oracle_result* r) {
   std::free(r->levels);
   std::free(r->deadlocks);
   std::free(r->visited);
+  std::free(r->violations);
   r->levels = nullptr;
   r->deadlocks = nullptr;
   r->visited = nullptr;
+  r->violations = nullptr;
+}
+
+static void set_violations(const Plan& plan, std::vector<Vec>& viol, uint32_t level,
+                           oracle_result* out) {
+  std::sort(viol.begin(), viol.end(), vec_less);
+  out->n_violations = viol.size();
+  out->violations =
+      static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (viol.size() * plan.words + 1)));
+  for (size_t i = 0; i < viol.size(); ++i)
+    for (uint32_t k = 0; k < plan.words; ++k) out->violations[i * plan.words + k] = viol[i][k];
+  out->violation_level = level;
 }
 
 static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
@@ -340,6 +359,9 @@ static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
   for (size_t i = 0; i < dead.size(); ++i)
     for (uint32_t k = 0; k < plan.words; ++k) out->deadlocks[i * plan.words + k] = dead[i][k];
   out->visited = nullptr;
+  out->n_violations = 0;
+  out->violations = nullptr;
+  out->violation_level = 0xFFFFFFFFu;
   if (visited) {
     std::sort(visited->begin(), visited->end(), vec_less);
     out->visited = static_cast<uint32_t*>(
@@ -356,29 +378,54 @@ static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
 // max_levels > 0 the search stops once levels 0 .. max_levels-1 are known
 // (a BFS prefix: level counts of those levels, the states at distance below
 // max_levels, and transitions and deadlocks of the levels expanded so far).
-int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
-                   const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
-                   const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
-                   uint64_t max_states, uint32_t max_levels, int want_visited,
-                   oracle_result* out) {
+//
+// Safety monitor (Sec. 3: the negation of a safety property is an automaton
+// added to the network): with monitor_proc >= 0, a state violates the
+// property when the local state of process monitor_proc is marked in
+// monitor_bad (one byte per local state).  Every level is checked as soon as
+// it is complete; the violating states and the first level that holds one
+// are returned.  With stop_on_violation the search ends there: that level is
+// counted but not expanded.
+int oracle_explore_monitored(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                             const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                             const uint32_t* dst, uint32_t n_labels, uint32_t R,
+                             const int32_t* rules, uint64_t max_states, uint32_t max_levels,
+                             int want_visited, int32_t monitor_proc, const uint8_t* monitor_bad,
+                             int stop_on_violation, oracle_result* out) {
   Net net;
   Plan plan;
   if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
                           &net))
     return -1;
   if (!make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
+  if (monitor_proc >= 0 && (uint32_t(monitor_proc) >= P || !monitor_bad)) return -1;
 
   VecSet visited;
-  std::vector<Vec> frontier, next, dead;
+  std::vector<Vec> frontier, next, dead, viol;
   std::vector<uint64_t> levels;
   uint64_t transitions = 0;
+  uint32_t viol_level = 0xFFFFFFFFu;
   std::vector<std::vector<uint32_t>> succ;
+  auto violates = [&](const Vec& v) {
+    return monitor_proc >= 0 && monitor_bad[unpack(plan, v)[monitor_proc]] != 0;
+  };
+  // record the violating states of the level just completed
+  auto check_level = [&](const std::vector<Vec>& level) {
+    for (const Vec& v : level) {
+      if (violates(v)) {
+        viol.push_back(v);
+        if (viol_level == 0xFFFFFFFFu) viol_level = uint32_t(levels.size() - 1);
+      }
+    }
+  };
 
   Vec init = pack(plan, net.initial);
   visited.insert(init);
   frontier.push_back(init);
   levels.push_back(1);
+  check_level(frontier);
   while (!frontier.empty()) {
+    if (stop_on_violation && !viol.empty()) break;
     if (max_levels && levels.size() >= max_levels) break;
     next.clear();
     for (const Vec& s : frontier) {
@@ -391,14 +438,28 @@ int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial
       }
       if (max_states && visited.size() > max_states) return -2;
     }
-    if (!next.empty()) levels.push_back(next.size());
+    if (!next.empty()) {
+      levels.push_back(next.size());
+      check_level(next);
+    }
     frontier.swap(next);
   }
   std::vector<Vec> vis;
   if (want_visited) vis.assign(visited.begin(), visited.end());
   fill_result(plan, levels, visited.size(), transitions, dead, want_visited ? &vis : nullptr,
               out);
+  set_violations(plan, viol, viol_level, out);
   return 0;
+}
+
+int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                   const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                   const uint32_t* dst, uint32_t n_labels, uint32_t R, const int32_t* rules,
+                   uint64_t max_states, uint32_t max_levels, int want_visited,
+                   oracle_result* out) {
+  return oracle_explore_monitored(P, n_states, initial, n_trans, src, label, dst, n_labels, R,
+                                  rules, max_states, max_levels, want_visited, -1, nullptr, 0,
+                                  out);
 }
 
 // Product successors (Sec. 3), with multiplicity, of n packed states

@@ -193,6 +193,31 @@ def wide_rule(n_procs: int = 6, k: int = 5) -> Network:
     return _net([k + 1] * n_procs, [0] * n_procs, trans, 1, rules, f"wide_rule_{n_procs}x{k}")
 
 
+def random_monitor(seed: int, actions, n_states: int = 4, n_observed: int = 4):
+    """A seeded deterministic automaton over ``n_observed`` of the given action
+    names (a negated safety property to add to a network): states 0 ..
+    n_states-1, initial 0, one transition per (state, observed action) to a
+    uniform target.  Returns (n_states, initial, [(src, action, dst)])."""
+    rng = SplitMix64(seed)
+    pool = list(actions)
+    obs = []
+    while pool and len(obs) < n_observed:
+        obs.append(pool.pop(rng.below(len(pool))))
+    trans = [(m, a, rng.below(n_states)) for m in range(n_states) for a in obs]
+    return n_states, 0, trans
+
+
+def tick_counter(n0: int, others, k: int):
+    """Process 0 cycles through n0 states on action ``tick``; processes 1..
+    cycle through others[i] states on ``tau``; the automaton counts ticks up
+    to k and stays there (its state k is the bad one).  Returns (processes as
+    (n_states, initial, trans) triples, automaton triple)."""
+    procs = [(n0, 0, [(i, "tick", (i + 1) % n0) for i in range(n0)])]
+    procs += [(n, 0, [(i, "tau", (i + 1) % n) for i in range(n)]) for n in others]
+    mon = (k + 1, 0, [(m, "tick", min(m + 1, k)) for m in range(k + 1)])
+    return procs, mon
+
+
 def large_random_network(live: int = 8) -> Network:
     """The large plain-path workload: 12 processes of 64 declared local states
     (6-bit fields, so 3-word vectors), out-degree 3 with uniform targets, a
