@@ -224,7 +224,14 @@ typedef struct {
                                  chunk of successors (the per-block state cache
                                  of the paper's tool, Sec. 3); results are
                                  unchanged, table probes fewer                 */
-  uint32_t reserved[3];
+  uint32_t monitor_proc;      /* with monitor_bad: the process that is the
+                                 automaton of a negated safety property (Sec. 3) */
+  uint32_t stop_on_violation; /* nonzero: end the exploration after the first
+                                 level that holds a violation (that level is
+                                 counted, not expanded)                        */
+  uint32_t reserved;
+  const uint8_t* monitor_bad; /* host, n_states of monitor_proc bytes, nonzero
+                                 = bad local state; NULL: no safety check      */
 } gx_explore_opts;
 
 typedef struct {
@@ -237,6 +244,13 @@ typedef struct {
   uint32_t* deadlocks;    /* n_deadlocks x w words, sorted (library-owned)     */
   uint64_t local_duplicates; /* successors dropped by the local duplicate
                                 filter (gx_explore with local_dedup), else 0  */
+  uint64_t n_violations;  /* reachable states (of the levels found) whose
+                             monitor process is in a bad state; 0 without a
+                             monitor                                           */
+  uint32_t* violations;   /* n_violations x w words, sorted (library-owned)    */
+  uint32_t violation_level; /* first level holding a violation; 0xFFFFFFFF
+                               when none                                      */
+  uint32_t reserved;
 } gx_explore_result;
 
 /*
@@ -258,9 +272,19 @@ typedef struct {
  * successor-generation launch followed by one find-or-put-and-append launch
  * on opts->hip_stream.
  *
+ * Safety check (Sec. 3: the negation of a safety property is an automaton
+ * added to the network as one more process): with opts->monitor_bad set, a
+ * state whose local state of process opts->monitor_proc is marked bad is a
+ * violation.  Each level is scanned as soon as it is complete (one extra
+ * streaming pass over it); violations and the first level holding one are
+ * returned, and with opts->stop_on_violation the exploration ends there
+ * (that level is counted, not expanded; the table holds the states of the
+ * levels returned).
+ *
  * Synchronous: returns when the exploration ends.
  * Errors: GX_EINVAL (invalid network, word count mismatch, non-empty table,
- * network image too large for the kernel's LDS), GX_ETABLEFULL (a state
+ * network image too large for the kernel's LDS, monitor_proc out of range),
+ * GX_ETABLEFULL (a state
  * exhausted every hash function; exploration stops, no result), GX_ENOMEM
  * (frontier or deadlock buffer too small, or allocation failure).
  */

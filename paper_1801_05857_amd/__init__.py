@@ -79,7 +79,8 @@ class _Network(ctypes.Structure):
 class _ExploreOpts(ctypes.Structure):
     _fields_ = [("frontier_capacity", ctypes.c_uint64), ("deadlock_capacity", ctypes.c_uint64),
                 ("hip_stream", ctypes.c_void_p), ("local_dedup", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("monitor_proc", ctypes.c_uint32), ("stop_on_violation", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("monitor_bad", ctypes.c_void_p)]
 
 
 class _ExploreResult(ctypes.Structure):
@@ -87,7 +88,9 @@ class _ExploreResult(ctypes.Structure):
                 ("words_per_state", ctypes.c_uint32), ("n_levels", ctypes.c_uint32),
                 ("level_counts", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32)),
-                ("local_duplicates", ctypes.c_uint64)]
+                ("local_duplicates", ctypes.c_uint64),
+                ("n_violations", ctypes.c_uint64), ("violations", ctypes.POINTER(ctypes.c_uint32)),
+                ("violation_level", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _BatchOpts(ctypes.Structure):
@@ -375,6 +378,8 @@ class ExploreResult:
     levels: np.ndarray
     deadlocks: np.ndarray
     local_duplicates: int = 0
+    violations: np.ndarray = None  # (n, w) uint32, sorted (safety monitor)
+    violation_level: int | None = None
 
 
 def _take_result(res: _ExploreResult) -> ExploreResult:
@@ -384,18 +389,32 @@ def _take_result(res: _ExploreResult) -> ExploreResult:
         dead = np.ctypeslib.as_array(res.deadlocks, shape=(res.n_deadlocks * w,)).copy()
     else:
         dead = np.zeros(0, np.uint32)
+    if res.n_violations:
+        viol = np.ctypeslib.as_array(res.violations, shape=(res.n_violations * w,)).copy()
+    else:
+        viol = np.zeros(0, np.uint32)
+    vl = None if res.violation_level == 0xFFFFFFFF else int(res.violation_level)
     out = ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
-                        dead.reshape(-1, w), int(res.local_duplicates))
+                        dead.reshape(-1, w), int(res.local_duplicates), viol.reshape(-1, w), vl)
     lib().gx_explore_result_free(ctypes.byref(res))
     return out
 
 
 def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity: int = 0,
-            stream=None, local_dedup: bool = False) -> ExploreResult:
-    """gx_explore: BFS of the synchronous product into ``table``."""
+            stream=None, local_dedup: bool = False, monitor=None,
+            stop_on_violation: bool = False) -> ExploreResult:
+    """gx_explore: BFS of the synchronous product into ``table``.  monitor =
+    (process, bad flags per local state of it) checks a safety property."""
     h = _NetHolder(net)
+    proc, bad = 0, None
+    if monitor is not None:
+        proc = int(monitor[0])
+        bad = np.ascontiguousarray(np.asarray(monitor[1]).astype(np.uint8))
+        if not 0 <= proc < len(net.n_states) or bad.shape != (int(net.n_states[proc]),):
+            raise ValueError("monitor: a process index and one flag per local state of it")
     opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream),
-                        int(local_dedup))
+                        int(local_dedup), proc, int(stop_on_violation), 0,
+                        bad.ctypes.data if bad is not None else None)
     res = _ExploreResult()
     _check(lib().gx_explore(ctypes.byref(h.c), table.handle, ctypes.byref(opts),
                             ctypes.byref(res)), "gx_explore")

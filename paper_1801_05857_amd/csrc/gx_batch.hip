@@ -592,6 +592,8 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
       const uint32_t w = b->w[i];
       const gx::BatchState& st = hs[k];
       const uint64_t flags = st.ctr[gx::kCtrFlags * gx::kCtrSpread];
+      outs[i] = gx_explore_result{};  // no safety monitor in batches
+      outs[i].violation_level = 0xFFFFFFFFu;
       gx_status s = GX_OK;
       if (!st.done || hg.abort)
         s = GX_EDEVICE;

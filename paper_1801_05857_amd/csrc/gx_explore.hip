@@ -1,19 +1,21 @@
 // Level-synchronous breadth-first exploration of the synchronous product of a
 // network of LTSs (Sec. 3 of the paper), built on the bucketed find-or-put.
 //
-// Per BFS level one kernel launch expands the current frontier:
-//   1. a workgroup of 256 threads takes 256 frontier states, one per thread,
-//      and counts each state's product successors from the LDS-resident
-//      network image; a state with none is a deadlock;
-//   2. a block-wide prefix sum of the counts gives every successor a slot;
-//      successors are generated into an LDS staging buffer, in chunks when
-//      the tile has more successors than the buffer holds;
-//   3. subgroups of G lanes find-or-put the staged successors; those reported
-//      NEW are appended to the next frontier with one atomic add per
-//      wavefront (ballot + popcount ranks).
+// A level is expanded in slices; each slice is two kernels on the caller's
+// stream:
+//   1. gen_level_kernel: 256 frontier states per workgroup, one per lane;
+//      every lane counts its state's product successors from the
+//      LDS-resident network image (none: a deadlock, recorded at once), one
+//      atomic add per workgroup reserves their room in the successor buffer,
+//      and the wavefront writes them with coalesced stores;
+//   2. append_kernel: find-or-put of the successor buffer by subgroups of G
+//      lanes; NEW states are gathered per wavefront in LDS and moved to the
+//      next frontier with one atomic add and coalesced stores.
 // The paper's tool scans the hash table for states still to explore and keeps
 // a per-block cache of new states (Sec. 3); here the next level is an explicit
-// compacted frontier, so no scan of the table is needed.
+// compacted frontier, so no scan of the table is needed.  With a safety
+// monitor, every completed level is scanned once for states whose monitor
+// process is in a bad state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -209,6 +211,60 @@ void pack_host(const NetImage& ni, const uint32_t* local, uint32_t* out) {
 
 namespace {
 
+// Safety monitor: the states among states[0, n) whose monitor field f (word
+// | shift << 8 | width << 16) holds a local state marked in the bitmask
+// `bad` are counted in *ctr and, below cap, copied to out (S words each).
+// One atomic add per wavefront that finds any.
+template <int S>
+__global__ __launch_bounds__(256) void monitor_scan_kernel(const uint32_t* states, uint64_t n,
+                                                           uint32_t f, const uint32_t* bad,
+                                                           uint32_t* out, uint64_t cap,
+                                                           unsigned long long* ctr) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
+  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
+  const int lane = __lane_id();
+  for (uint64_t base = first; base < n; base += stride) {  // wavefront-uniform
+    const uint64_t i = base + lane;
+    uint32_t sw[S] = {};
+    bool hit = false;
+    if (i < n) {
+      load_slot<S>(states + i * S, sw);
+      const uint32_t l = get_field<S>(sw, f);
+      hit = (bad[l >> 5] >> (l & 31)) & 1u;
+    }
+    const uint64_t m = __ballot(hit);
+    if (m == 0) continue;
+    unsigned long long k = 0;
+    if (lane == 0) k = atomicAdd(ctr, static_cast<unsigned long long>(__popcll(m)));
+    k = __shfl(k, 0, 64) + __popcll(m & ((1ull << lane) - 1ull));
+    if (hit && k < cap) store_slot<S>(out + k * S, sw);
+  }
+}
+
+hipError_t launch_monitor_scan(uint32_t S, const uint32_t* states, uint64_t n, uint32_t f,
+                               const uint32_t* bad, uint32_t* out, uint64_t cap, uint64_t* ctr,
+                               uint32_t cus, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid =
+      static_cast<uint32_t>(std::min<uint64_t>((n + 255) / 256, static_cast<uint64_t>(cus) * 8));
+  auto* c = reinterpret_cast<unsigned long long*>(ctr);
+  switch (S) {
+    case 1:
+      hipLaunchKernelGGL((monitor_scan_kernel<1>), dim3(grid), dim3(256), 0, s, states, n, f, bad,
+                         out, cap, c);
+      break;
+    case 2:
+      hipLaunchKernelGGL((monitor_scan_kernel<2>), dim3(grid), dim3(256), 0, s, states, n, f, bad,
+                         out, cap, c);
+      break;
+    default:
+      hipLaunchKernelGGL((monitor_scan_kernel<4>), dim3(grid), dim3(256), 0, s, states, n, f, bad,
+                         out, cap, c);
+      break;
+  }
+  return hipGetLastError();
+}
+
 // One slice of a level: successor generation, then find-or-put-and-append.
 hipError_t launch_slice(const gx_table* t, const GenArgs& g, uint32_t grid, size_t lds,
                         const AppendArgs& ap, uint32_t cus, hipStream_t s) {
@@ -291,8 +347,10 @@ void gx_explore_result_free(gx_explore_result* r) {
   if (!r) return;
   std::free(r->level_counts);
   std::free(r->deadlocks);
+  std::free(r->violations);
   r->level_counts = nullptr;
   r->deadlocks = nullptr;
+  r->violations = nullptr;
 }
 
 gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* opts,
@@ -302,6 +360,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   gx_status s = gx::compile_network(net, &ni);
   if (s != GX_OK) return s;
   if (ni.words != t->w) return GX_EINVAL;
+  const bool monitor = opts && opts->monitor_bad;
+  if (monitor && opts->monitor_proc >= ni.field.size()) return GX_EINVAL;
   const uint32_t S = t->S;
   const size_t state_bytes = S * sizeof(uint32_t);
   // 0: limited only by device memory
@@ -363,6 +423,47 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   if (st0 == gx::kFull) return GX_ETABLEFULL;
   if (st0 != gx::kNew) return GX_EINVAL;
 
+  // Safety monitor: a bitmask of the bad local states of the monitor
+  // process; every completed level is scanned for states holding one.  The
+  // initial state (level 0) is checked here.
+  uint32_t mon_field = 0;
+  std::vector<uint32_t> mon_mask;
+  bool init_violates = false;
+  uint32_t viol_level = 0xFFFFFFFFu;
+  uint64_t viol_total = 0;  // violating states the device has recorded
+  bool stop = false;
+  if (monitor) {
+    const uint32_t mp = opts->monitor_proc;
+    const uint32_t n_local = net->procs[mp].n_states;
+    mon_mask.assign((n_local + 31) / 32, 0u);
+    for (uint32_t l = 0; l < n_local; ++l)
+      if (opts->monitor_bad[l]) mon_mask[l >> 5] |= 1u << (l & 31);
+    if (eb.mon_cap < mon_mask.size()) {
+      if (eb.mon) (void)hipFree(eb.mon);
+      eb.mon = nullptr;
+      eb.mon_cap = 0;
+      if (hipMalloc(&eb.mon, mon_mask.size() * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GX_ENOMEM;
+      }
+      eb.mon_cap = mon_mask.size();
+    }
+    if (!eb.viol_ctr && hipMalloc(&eb.viol_ctr, sizeof(uint64_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return GX_ENOMEM;
+    }
+    if (hipMemcpy(eb.mon, mon_mask.data(), mon_mask.size() * sizeof(uint32_t),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(eb.viol_ctr, 0, sizeof(uint64_t), stream) != hipSuccess)
+      return GX_EDEVICE;
+    mon_field = ni.field[mp];
+    if (opts->monitor_bad[ni.initial[mp]]) {
+      init_violates = true;
+      viol_level = 0;
+      stop = opts->stop_on_violation != 0;
+    }
+  }
+
   gx::GenArgs g;
   g.img = eb.img;
   g.img_words = img_words;
@@ -404,7 +505,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   uint64_t dead_known = 0;
   constexpr uint64_t kTargetSlice = 1u << 22;  // 16384 workgroups per launch
   constexpr uint64_t kMaxRoom = 1ull << 28;    // states of frontier room one slice may claim
-  while (n_in > 0) {
+  while (n_in > 0 && !stop) {
     const int nxt = cur ^ 1;
     if (hipMemsetAsync(eb.ctr + gx::kCtrTail * gx::kCtrSpread, 0, sizeof(uint64_t), stream) !=
         hipSuccess)
@@ -475,6 +576,31 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     dead_known = ctr(gx::kCtrDead);
     n_in = ctr(gx::kCtrTail);
     if (n_in) levels.push_back(n_in);
+    if (monitor && n_in) {
+      // scan the level just completed; if the record buffer was short, grow
+      // it (keeping earlier levels' records) and scan the level again
+      const uint64_t prev = viol_total;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (gx::launch_monitor_scan(S, eb.f[nxt], n_in, mon_field, eb.mon, eb.viol, eb.viol_cap,
+                                    eb.viol_ctr, static_cast<uint32_t>(cus), stream) !=
+            hipSuccess)
+          return GX_EDEVICE;
+        uint64_t got = 0;
+        if (hipMemcpyAsync(&got, eb.viol_ctr, sizeof(got), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+          return GX_EDEVICE;
+        viol_total = got;
+        if (got <= eb.viol_cap) break;
+        if ((s = grow_buf(&eb.viol, &eb.viol_cap, got, prev, ~0ull)) != GX_OK) return s;
+        if (hipMemcpy(eb.viol_ctr, &prev, sizeof(prev), hipMemcpyHostToDevice) != hipSuccess)
+          return GX_EDEVICE;
+      }
+      if (viol_total > prev) {
+        if (viol_level == 0xFFFFFFFFu) viol_level = static_cast<uint32_t>(levels.size() - 1);
+        if (opts->stop_on_violation) stop = true;
+      }
+    }
     cur = nxt;
   }
   const uint64_t n_dead = ctr(gx::kCtrDead);
@@ -512,6 +638,33 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   out->n_deadlocks = n_dead;
   out->deadlocks = dd;
   out->local_duplicates = ctr(gx::kCtrDups);
+  out->n_violations = 0;
+  out->violations = nullptr;
+  out->violation_level = viol_level;
+  if (monitor) {
+    std::vector<uint32_t> vraw(viol_total * S);
+    if (viol_total && hipMemcpy(vraw.data(), eb.viol, vraw.size() * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost) != hipSuccess) {
+      gx_explore_result_free(out);
+      return GX_EDEVICE;
+    }
+    std::vector<std::array<uint32_t, 4>> vl(viol_total);
+    for (uint64_t i = 0; i < viol_total; ++i) {
+      vl[i] = {0, 0, 0, 0};
+      for (uint32_t k = 0; k < t->w; ++k) vl[i][k] = vraw[i * S + k];
+    }
+    if (init_violates) vl.push_back({init[0], init[1], init[2], init[3]});
+    std::sort(vl.begin(), vl.end());
+    uint32_t* vv = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (vl.size() * t->w + 1)));
+    if (!vv) {
+      gx_explore_result_free(out);
+      return GX_ENOMEM;
+    }
+    for (size_t i = 0; i < vl.size(); ++i)
+      for (uint32_t k = 0; k < t->w; ++k) vv[i * t->w + k] = vl[i][k];
+    out->n_violations = vl.size();
+    out->violations = vv;
+  }
   return GX_OK;
 }
 

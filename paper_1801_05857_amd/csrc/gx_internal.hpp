@@ -22,6 +22,12 @@ struct gx_explore_buffers {
   uint64_t* ctr = nullptr;  // level counters, one cache line each
   uint8_t* status = nullptr;
   uint32_t* key = nullptr;  // 4 words
+  // safety monitor: bad-state bitmask, violating states, their running count
+  uint32_t* mon = nullptr;
+  uint64_t mon_cap = 0;      // words
+  uint32_t* viol = nullptr;
+  uint64_t viol_cap = 0;     // states
+  uint64_t* viol_ctr = nullptr;
 };
 
 struct gx_table {

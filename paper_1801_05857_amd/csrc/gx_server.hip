@@ -304,6 +304,7 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
       r->result.level_counts = L;
       r->result.n_deadlocks = n_dead;
       r->result.deadlocks = D;
+      r->result.violation_level = 0xFFFFFFFFu;  // no safety monitor in the server
       s->stats.states += total;
     } else {
       std::free(L);

@@ -117,7 +117,8 @@ void free_table(gx_table* t) {
   for (void* p : {static_cast<void*>(e.img), static_cast<void*>(e.f[0]),
                   static_cast<void*>(e.f[1]), static_cast<void*>(e.dead), static_cast<void*>(e.succ),
                   static_cast<void*>(e.ctr), static_cast<void*>(e.status),
-                  static_cast<void*>(e.key)})
+                  static_cast<void*>(e.key), static_cast<void*>(e.mon),
+                  static_cast<void*>(e.viol), static_cast<void*>(e.viol_ctr)})
     if (p) (void)hipFree(p);
   delete t;
 }
