@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="served exploration: Poisson request streams at several rates")
     ap.add_argument("--serve-n", type=int, default=120, help="requests per rate")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="served exploration at 0.1-1.2x the saturation rate, 1000 requests each")
     ap.add_argument("--dup-sweep", action="store_true",
                     help="isolated insertion of 2^27 one-word keys at duplication 1..64")
     ap.add_argument("--token-ring", action="store_true",
@@ -409,12 +411,14 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
         "configs": {f"B{B}-G{G}-U{U}": c for (B, G, U), c in Counter(cfgs).items()}}}
 
 
-def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
+def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0), relative="alone"):
     """Served exploration: Poisson arrivals of requests with reachable sizes
     spread log-uniformly over 1e4-1.4e8 (token rings of 7-15 nodes, sizes
     known in closed form) plus three- and four-word random networks; the
     declared bound is 1.25x the size.  Rates are multiples of the rate at
-    which the server completes them back to back (measured first)."""
+    which the server completes them back to back (relative="alone") or of
+    its saturation rate, all requests submitted at once ("saturation"); both
+    are measured first."""
     import random
 
     rng = random.Random(seed)
@@ -425,7 +429,7 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
              W.random_lts(404, 16, 64, 2, 3, 32, 0.25, 0.0)]
     out = []
     with gx.Server(200 << 30, max_hashes=16) as srv:
-        # sizes of the random networks, and a warm pool of resident tables
+        # sizes of the random networks
         for nt in extra:
             rid = srv.submit(nt, 1 << 20)
             st, r, _ = srv.poll(rid)
@@ -460,11 +464,27 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
         for nt, sz in reqs:
             srv.poll(srv.submit(nt, int(sz * 1.25)))
         alone = time.perf_counter() - t0
-        rate_sat = n_req / alone
+        rate_alone = n_req / alone
         out.append({"served": "one at a time", "requests": n_req, "seconds": round(alone, 3),
                     "states_per_s": round(total_states / alone)})
+        # all at once: the saturation rate
+        t0 = time.perf_counter()
+        ids = [srv.submit(nt, int(sz * 1.25)) for nt, sz in reqs]
+        burst_bad = 0
+        for rid, (nt, sz) in zip(ids, reqs):
+            st, r, _ = srv.poll(rid)
+            burst_bad += int(st != gx.GX_OK or r.n_states != sz)
+        burst = time.perf_counter() - t0
+        rate_sat = n_req / burst
+        out.append({"served": "all submitted at once (saturation)", "requests": n_req,
+                    "seconds": round(burst, 3), "states_per_s": round(total_states / burst),
+                    "requests_per_s": round(rate_sat, 2), "wrong_results": burst_bad,
+                    "vs_one_call_per_request": round(single / burst, 2)})
+        print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+        base = rate_sat if relative == "saturation" else rate_alone
+        label = "saturation" if relative == "saturation" else "one-at-a-time"
         for mult in rates:
-            lam = mult * rate_sat
+            lam = mult * base
             t_arr = 0.0
             times = []
             for _ in range(n_req):
@@ -486,7 +506,7 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
             wall = time.perf_counter() - start
             lat.sort()
             stt = srv.stats()
-            out.append({"served": f"Poisson, rate {mult}x the one-at-a-time rate",
+            out.append({"served": f"Poisson, rate {mult}x the {label} rate",
                         "requests": n_req, "rate_per_s": round(lam, 2),
                         "seconds": round(wall, 3), "states_per_s": round(total_states / wall),
                         "p50_latency_s": round(lat[len(lat) // 2], 4),
@@ -494,6 +514,7 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0)):
                         "wrong_results": bad, "active_peak": stt["active_peak"],
                         "retried": stt["retried"],
                         "vs_one_call_per_request": round(single / wall, 2)})
+            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
 
 
@@ -548,6 +569,11 @@ def main():
         return
     if args.serve:
         for row in run_serve(gx, torch, W, args.serve_n):
+            print(json.dumps(row), flush=True)
+        return
+    if args.serve_sweep:
+        for row in run_serve(gx, torch, W, max(args.serve_n, 1000),
+                             rates=(0.1, 0.25, 0.5, 0.75, 1.0, 1.2), relative="saturation"):
             print(json.dumps(row), flush=True)
         return
 
@@ -694,9 +720,12 @@ def main():
             "workload": ("Poisson request streams (token rings of 7-15 nodes and two random "
                          "networks, 1e4-1.4e8 states, 1-4 words), bound declared 1.25x"),
             "one_call_per_request_states_per_s": rows[0]["states_per_s"],
+            "saturation": {k: rows[2][k] for k in ("requests_per_s", "states_per_s",
+                                                   "wrong_results",
+                                                   "vs_one_call_per_request")},
             "rates": [{k: r[k] for k in ("rate_per_s", "states_per_s", "p50_latency_s",
                                          "p99_latency_s", "wrong_results",
-                                         "vs_one_call_per_request")} for r in rows[2:]]}
+                                         "vs_one_call_per_request")} for r in rows[3:]]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
         if not args.no_explore:

@@ -377,9 +377,11 @@ gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bu
  * Exploration server.  Requests (a network and a declared bound on its number
  * of reachable states) are admitted when their HBM reservation fits the
  * budget: a table with ceil(bound / load_factor) slots rounded up to a power
- * of two, two frontier buffers and a deadlock buffer of as many states.  An
- * admitted request takes a resident table from a pool (cleared, never freed
- * between requests).  A host thread runs steps: one launch per slot width
+ * of two, two frontier buffers and a deadlock buffer of as many states, one
+ * power-of-two block of a device arena of budget_bytes that the server
+ * allocates once at creation (a buddy allocator: admission allocates
+ * nothing; the largest reservation that can ever fit is the largest power
+ * of two within the budget).  A host thread runs steps: one launch per slot width
  * expands the current BFS level of every admitted request, so requests that
  * arrive while others run join at the next step (continuous batching).  A
  * request whose table fills up is retried with four times its bound (at
@@ -389,7 +391,8 @@ gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bu
 typedef struct gx_server gx_server;
 
 typedef struct {
-  uint64_t budget_bytes;      /* HBM the server may reserve (tables, frontiers) */
+  uint64_t budget_bytes;      /* HBM of the server's arena (tables, frontiers),
+                                 allocated at creation                         */
   uint32_t max_active;        /* requests admitted at once; 0 -> 256           */
   uint32_t max_hashes;        /* H; 0 -> 8                                     */
   double load_factor;         /* table load at the declared bound; 0 -> 0.5   */
@@ -407,7 +410,7 @@ typedef struct {
   uint64_t active_peak;    /* largest number of requests admitted at once       */
   uint64_t reserved_peak;  /* largest reservation held (bytes)                  */
   uint64_t states;         /* reachable states of completed requests            */
-  uint64_t reserved_now, pooled_bytes, waiting;
+  uint64_t reserved_now, pooled_bytes /* arena bytes not reserved */, waiting;
 } gx_server_stats;
 
 /* Start a server on the current device (spawns its step thread). */

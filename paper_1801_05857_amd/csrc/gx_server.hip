@@ -1,9 +1,11 @@
 // Exploration server: requests (networks with a declared size bound) are
-// admitted when their HBM reservation fits the budget, get a resident table
-// from a pool (cleared, never freed between requests), and are advanced one
-// BFS level per step by a multi-job launch over every active request
-// (continuous batching: requests join and leave between steps).  A request
-// whose table fills up is retried with four times its bound.
+// admitted when their HBM reservation fits the budget, get their table,
+// frontiers and deadlock buffer as one block of a device arena allocated
+// once with the server (a buddy allocator: reservations are powers of two,
+// so admitting a request allocates nothing), and are advanced one BFS level
+// per step by a multi-job launch over every active request (continuous
+// batching: requests join and leave between steps).  A request whose table
+// fills up is retried with four times its bound.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +20,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -63,14 +66,88 @@ uint64_t pow2_at_least(uint64_t x) {
   return p;
 }
 
+// Buddy allocator over [0, size): the range is cut into power-of-two top
+// blocks, largest first (each at an offset that is a multiple of its size),
+// and every allocation is a power-of-two block of at least kMin bytes, split
+// from the smallest free block that holds it; a freed block merges with its
+// free buddy up to its top block.
+class Buddy {
+ public:
+  static constexpr int kMinShift = 12;  // 4 KiB
+  void init(uint64_t size) {
+    free_.assign(64, {});
+    tops_.clear();
+    uint64_t off = 0;
+    for (int o = 63 - kMinShift; o >= 0; --o) {
+      const uint64_t b = uint64_t(1) << (o + kMinShift);
+      if (size - off >= b) {
+        tops_.push_back({off, o});
+        free_[o].insert(off);
+        off += b;
+      }
+    }
+  }
+  uint64_t largest() const {
+    return tops_.empty() ? 0 : uint64_t(1) << (tops_.front().second + kMinShift);
+  }
+  // offset of a block of at least n bytes, or ~0 when none is free
+  uint64_t alloc(uint64_t n) {
+    const int o = order(n);
+    int k = o;
+    while (k < 64 && free_[k].empty()) ++k;
+    if (k >= 64) return ~0ull;
+    const uint64_t off = *free_[k].begin();
+    free_[k].erase(free_[k].begin());
+    while (k > o) {
+      --k;
+      free_[k].insert(off + (uint64_t(1) << (k + kMinShift)));
+    }
+    return off;
+  }
+  void release(uint64_t off, uint64_t n) {
+    int o = order(n);
+    const int top = top_order(off);
+    while (o < top) {
+      const uint64_t buddy = off ^ (uint64_t(1) << (o + kMinShift));
+      auto it = free_[o].find(buddy);
+      if (it == free_[o].end()) break;
+      free_[o].erase(it);
+      off = std::min(off, buddy);
+      ++o;
+    }
+    free_[o].insert(off);
+  }
+  static uint64_t block_bytes(uint64_t n) { return uint64_t(1) << (order(n) + kMinShift); }
+
+ private:
+  static int order(uint64_t n) {
+    int o = 0;
+    while ((uint64_t(1) << (o + kMinShift)) < n) ++o;
+    return o;
+  }
+  int top_order(uint64_t off) const {
+    for (const auto& t : tops_)
+      if (off >= t.first && off < t.first + (uint64_t(1) << (t.second + kMinShift)))
+        return t.second;
+    return 0;
+  }
+  std::vector<std::set<uint64_t>> free_;
+  std::vector<std::pair<uint64_t, int>> tops_;  // offset, order
+};
+
+// Device words a job's small state takes: table counters, the initial key
+// and its status byte.
+constexpr uint64_t kSlotSmallBytes = 128;
+
 }  // namespace
 }  // namespace gx
 
 struct gx_server {
   struct Job {
     gx::Request* r = nullptr;
-    gx_table* t = nullptr;
-    uint64_t reserved = 0;
+    gx_table* t = nullptr;   // a view of its arena block
+    uint64_t reserved = 0;   // bytes of that block
+    uint64_t block = 0;      // its offset in the arena
     uint64_t n_in = 0;
     int cur = 0;
     uint32_t slot = 0;
@@ -92,9 +169,14 @@ struct gx_server {
   uint64_t next_id = 1;
   std::map<uint64_t, std::unique_ptr<gx::Request>> reqs;
   std::deque<gx::Request*> waiting;
-  std::vector<gx_table*> pool;  // idle resident tables
-  uint64_t pool_bytes = 0;
   uint64_t reserved = 0;        // bytes reserved by active jobs
+  // device arena of budget bytes, shared hash constants, per-slot small state
+  char* arena = nullptr;
+  uint64_t arena_bytes = 0;
+  gx::Buddy buddy;
+  uint64_t a0 = 0, c0 = 0;  // first hash constant pair (host copy)
+  uint64_t* d_hc = nullptr;
+  char* d_small = nullptr;
   gx_server_stats stats{};
   // owned by the step thread
   std::vector<Job> active;
@@ -113,39 +195,6 @@ uint64_t table_bytes_for(uint32_t w, uint64_t slots) {
   return 4ull * slots * slot_words(w) * sizeof(uint32_t);
 }
 
-gx_status ensure_buffers(gx_table* t, uint64_t states) {
-  gx_explore_buffers& eb = t->eb;
-  const size_t sb = t->S * sizeof(uint32_t);
-  for (int k = 0; k < 2; ++k) {
-    if (eb.f_cap[k] < states) {
-      if (eb.f[k]) (void)hipFree(eb.f[k]);
-      eb.f[k] = nullptr;
-      eb.f_cap[k] = 0;
-      if (hipMalloc(&eb.f[k], states * sb) != hipSuccess) {
-        (void)hipGetLastError();
-        return GX_ENOMEM;
-      }
-      eb.f_cap[k] = states;
-    }
-  }
-  if (eb.dead_cap < states) {
-    if (eb.dead) (void)hipFree(eb.dead);
-    eb.dead = nullptr;
-    eb.dead_cap = 0;
-    if (hipMalloc(&eb.dead, states * sb) != hipSuccess) {
-      (void)hipGetLastError();
-      return GX_ENOMEM;
-    }
-    eb.dead_cap = states;
-  }
-  if (!eb.key && (hipMalloc(&eb.key, 4 * sizeof(uint32_t)) != hipSuccess ||
-                  hipMalloc(&eb.status, 8) != hipSuccess)) {
-    (void)hipGetLastError();
-    return GX_ENOMEM;
-  }
-  return GX_OK;
-}
-
 void complete(gx_server* s, Request* r, gx_status st) {
   r->status = st;
   r->latency_ns = static_cast<uint64_t>(
@@ -157,41 +206,42 @@ void complete(gx_server* s, Request* r, gx_status st) {
   else ++s->stats.failed;
 }
 
-// Take a table for w words and `slots` slots: an idle pooled one of that
-// exact shape, else a new one (evicting idle tables while over budget).
-// Called with mu held.
-gx_table* take_table(gx_server* s, uint32_t w, uint64_t slots, uint64_t need) {
+// A table over the arena block at `off` for w words and `slots` slots (a
+// power of two): the table, then the two frontiers and the deadlock buffer,
+// slots states each; counters, initial key and status in the job slot's
+// small state; the server's shared hash constants.  Nothing is allocated on
+// the device.  mu held.
+gx_table* job_table(gx_server* s, uint32_t w, uint64_t slots, uint64_t off, uint32_t slot) {
   const uint32_t S = slot_words(w);
   const uint32_t* c = s->cfg[S];
-  for (size_t k = 0; k < s->pool.size(); ++k) {
-    gx_table* t = s->pool[k];
-    if (t->w == w && t->B == c[0] && t->G == c[1] && t->U == c[2] &&
-        t->n_buckets * (t->B / t->S) == slots) {
-      s->pool.erase(s->pool.begin() + k);
-      s->pool_bytes -= table_bytes_for(w, slots);
-      return t;
-    }
+  gx_table* t = new (std::nothrow) gx_table;
+  if (!t) return nullptr;
+  t->device = s->device;
+  t->w = w;
+  t->S = S;
+  t->B = c[0];
+  t->G = c[1];
+  t->U = c[2];
+  t->H = s->H;
+  t->seed = s->seed;
+  t->n_buckets = slots * S / c[0];
+  t->a0 = s->a0;
+  t->c0 = s->c0;
+  const uint64_t T = slots * S * sizeof(uint32_t);
+  char* base = s->arena + off;
+  char* small = s->d_small + static_cast<uint64_t>(slot) * kSlotSmallBytes;
+  t->words = reinterpret_cast<uint32_t*>(base);
+  t->hc = s->d_hc;
+  t->counters = reinterpret_cast<uint64_t*>(small);  // kNumCounters words
+  t->eb.key = reinterpret_cast<uint32_t*>(small + 64);
+  t->eb.status = reinterpret_cast<uint8_t*>(small + 96);
+  for (int k = 0; k < 2; ++k) {
+    t->eb.f[k] = reinterpret_cast<uint32_t*>(base + (k + 1) * T);
+    t->eb.f_cap[k] = slots;
   }
-  while (!s->pool.empty() && s->reserved + s->pool_bytes + need > s->budget) {
-    gx_table* t = s->pool.front();
-    s->pool.erase(s->pool.begin());
-    s->pool_bytes -= table_bytes_for(t->w, t->n_buckets * (t->B / t->S));
-    gx_table_destroy(t);
-  }
-  gx_table_opts o{s->seed, s->H, c[1], c[2], 0};
-  gx_table* t = nullptr;
-  // capacity so that the table has exactly `slots` slots
-  if (gx_table_create(w, c[0], slots, &o, &t) != GX_OK) return nullptr;
-  if (ensure_buffers(t, slots) != GX_OK) {
-    gx_table_destroy(t);
-    return nullptr;
-  }
+  t->eb.dead = reinterpret_cast<uint32_t*>(base + 3 * T);
+  t->eb.dead_cap = slots;
   return t;
-}
-
-void release_table(gx_server* s, gx_table* t) {  // mu held
-  s->pool.push_back(t);
-  s->pool_bytes += table_bytes_for(t->w, t->n_buckets * (t->B / t->S));
 }
 
 // Admit waiting requests while their reservations fit.  mu held.
@@ -201,21 +251,18 @@ void admit(gx_server* s) {
     const uint64_t slots = pow2_at_least(
         std::max<uint64_t>(64, static_cast<uint64_t>(static_cast<double>(r->declared) / s->load) + 1));
     const uint64_t need = table_bytes_for(r->w, slots);
-    if (need > s->budget) {  // can never fit
+    if (need > s->buddy.largest()) {  // can never fit
       s->waiting.pop_front();
       complete(s, r, GX_ENOMEM);
       s->cv_done.notify_all();
       continue;
     }
-    if (s->reserved + need > s->budget) break;  // wait for running jobs to finish
-    gx_table* t = take_table(s, r->w, slots, need);
+    const uint64_t off = s->buddy.alloc(need);
+    if (off == ~0ull) break;  // wait for running jobs to finish
+    const uint32_t slot = s->free_slots.back();
+    gx_table* t = job_table(s, r->w, slots, off, slot);
     if (!t) {
-      if (s->active.empty()) {
-        s->waiting.pop_front();
-        complete(s, r, GX_ENOMEM);
-        s->cv_done.notify_all();
-        continue;
-      }
+      s->buddy.release(off, need);
       break;
     }
     s->waiting.pop_front();
@@ -223,7 +270,8 @@ void admit(gx_server* s) {
     j.r = r;
     j.t = t;
     j.reserved = need;
-    j.slot = s->free_slots.back();
+    j.block = off;
+    j.slot = slot;
     s->free_slots.pop_back();
     s->reserved += need;
     s->stats.reserved_peak = std::max(s->stats.reserved_peak, s->reserved);
@@ -246,7 +294,8 @@ void admit(gx_server* s) {
     if (!ok) {
       s->reserved -= need;
       s->free_slots.push_back(j.slot);
-      release_table(s, t);
+      s->buddy.release(off, need);
+      delete t;
       complete(s, r, GX_EDEVICE);
       s->cv_done.notify_all();
       continue;
@@ -314,7 +363,8 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
   }
   s->reserved -= j.reserved;
   s->free_slots.push_back(j.slot);
-  release_table(s, j.t);
+  s->buddy.release(j.block, j.reserved);
+  delete j.t;  // a view: its memory stays in the arena
   s->active.erase(s->active.begin() + k);
 }
 
@@ -425,12 +475,14 @@ void destroy_server(gx_server* s) {
     s->th.join();
   }
   (void)hipDeviceSynchronize();
-  for (auto& j : s->active) gx_table_destroy(j.t);
-  for (gx_table* t : s->pool) gx_table_destroy(t);
+  for (auto& j : s->active) delete j.t;
   for (auto& kv : s->reqs) gx_explore_result_free(&kv.second->result);
   if (s->d_jobs) (void)hipFree(s->d_jobs);
   if (s->d_img) (void)hipFree(s->d_img);
   if (s->d_ctr) (void)hipFree(s->d_ctr);
+  if (s->arena) (void)hipFree(s->arena);
+  if (s->d_hc) (void)hipFree(s->d_hc);
+  if (s->d_small) (void)hipFree(s->d_small);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   s->cv_done.notify_all();
   delete s;
@@ -500,6 +552,29 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
     gx::destroy_server(s);
     return GX_ENOMEM;
   }
+  // the arena (allocated once: admission allocates nothing), the hash
+  // constants every job table shares, and each job slot's small state
+  {
+    const uint64_t arena_bytes = s->budget & ~((uint64_t(1) << gx::Buddy::kMinShift) - 1);
+    std::vector<uint64_t> hc(2 * s->H);
+    for (uint32_t j = 0; j < s->H; ++j) gx::hash_constants(s->seed, j, &hc[2 * j], &hc[2 * j + 1]);
+    s->a0 = hc[0];
+    s->c0 = hc[1];
+    if (arena_bytes == 0 || hipMalloc(&s->arena, arena_bytes) != hipSuccess ||
+        hipMalloc(&s->d_hc, hc.size() * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&s->d_small, gx::kSlotSmallBytes * s->max_active) != hipSuccess) {
+      (void)hipGetLastError();
+      gx::destroy_server(s);
+      return GX_ENOMEM;
+    }
+    if (hipMemcpy(s->d_hc, hc.data(), hc.size() * sizeof(uint64_t), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      gx::destroy_server(s);
+      return GX_EDEVICE;
+    }
+    s->arena_bytes = arena_bytes;
+    s->buddy.init(arena_bytes);
+  }
   for (uint32_t k = s->max_active; k-- > 0;) s->free_slots.push_back(k);
   try {
     s->th = std::thread(gx::step_loop, s);
@@ -558,7 +633,7 @@ gx_status gx_server_get_stats(gx_server* s, gx_server_stats* out) {
   std::lock_guard<std::mutex> lock(s->mu);
   *out = s->stats;
   out->reserved_now = s->reserved;
-  out->pooled_bytes = s->pool_bytes;
+  out->pooled_bytes = s->arena_bytes - s->reserved;
   out->waiting = s->waiting.size();
   return GX_OK;
 }
