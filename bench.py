@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="served exploration: Poisson request streams at several rates")
     ap.add_argument("--serve-n", type=int, default=120, help="requests per rate")
+    ap.add_argument("--tiny", action="store_true",
+                    help="only the tiny configuration")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="served exploration at 0.1-1.2x the saturation rate, 1000 requests each")
     ap.add_argument("--dup-sweep", action="store_true",
@@ -570,6 +572,9 @@ def main():
     if args.serve:
         for row in run_serve(gx, torch, W, args.serve_n):
             print(json.dumps(row), flush=True)
+        return
+    if args.tiny:
+        print(json.dumps(run_tiny(gx, torch, W)), flush=True)
         return
     if args.serve_sweep:
         for row in run_serve(gx, torch, W, max(args.serve_n, 1000),
