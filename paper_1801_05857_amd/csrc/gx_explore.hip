@@ -268,8 +268,7 @@ hipError_t launch_monitor_scan(uint32_t S, const uint32_t* states, uint64_t n, u
 // One slice of a level: successor generation, then find-or-put-and-append.
 hipError_t launch_slice(const gx_table* t, const GenArgs& g, uint32_t grid, size_t lds,
                         const AppendArgs& ap, uint32_t cus, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(g.ctr + kCtrSucc * kCtrSpread, 0, sizeof(uint64_t), s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   switch (t->S) {
     case 1:
       if ((e = launch_gen<1>(g, grid, lds, s)) != hipSuccess) return e;
@@ -473,7 +472,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   gx::AppendArgs ap;
   ap.t = t->dev();
   ap.keys = nullptr;
-  ap.n_keys = eb.ctr + gx::kCtrSucc * gx::kCtrSpread;
+  ap.n_keys = nullptr;  // per slice: the successor counter its generation uses
   ap.ctr = eb.ctr;
   const uint32_t dedup_words =
       g.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
@@ -505,11 +504,9 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   uint64_t dead_known = 0;
   constexpr uint64_t kTargetSlice = 1u << 22;  // 16384 workgroups per launch
   constexpr uint64_t kMaxRoom = 1ull << 28;    // states of frontier room one slice may claim
+  uint64_t slice_no = 0;  // successor counters alternate from slice to slice
   while (n_in > 0 && !stop) {
     const int nxt = cur ^ 1;
-    if (hipMemsetAsync(eb.ctr + gx::kCtrTail * gx::kCtrSpread, 0, sizeof(uint64_t), stream) !=
-        hipSuccess)
-      return GX_EDEVICE;
     uint64_t tail_known = 0, bound = 0, dead_bound = dead_known, pos = 0;
     while (pos < n_in) {
       // full slices, but never more than kMaxRoom states of frontier room
@@ -564,6 +561,11 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       ap.keys_cap = eb.succ_cap;
       ap.frontier_out = eb.f[nxt];
       ap.cap_out = f_cap();
+      // the first slice's generation clears the next-frontier tail; each
+      // slice's clears the other successor counter for the next slice
+      g.reset_tail = pos == 0 ? 1u : 0u;
+      g.succ_ctr = (slice_no++ & 1) ? gx::kCtrSuccAlt : gx::kCtrSucc;
+      ap.n_keys = eb.ctr + g.succ_ctr * gx::kCtrSpread;
       const uint64_t grid = (run + 255) / 256;
       if (gx::launch_slice(t, g, static_cast<uint32_t>(grid), lds, ap, static_cast<uint32_t>(cus),
                            stream) != hipSuccess)

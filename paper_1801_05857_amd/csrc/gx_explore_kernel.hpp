@@ -237,7 +237,7 @@ __device__ inline void wave_lds_sync() {
 // counters sharing a line would serialise at one L2 atomic unit.
 constexpr uint32_t kCtrSpread = 16;
 enum : uint32_t { kCtrTail = 0, kCtrDead = 1, kCtrTrans = 2, kCtrFlags = 3, kCtrDups = 4,
-                  kCtrSucc = 5, kCtrCount = 6 };
+                  kCtrSucc = 5, kCtrSuccAlt = 6, kCtrCount = 7 };
 
 __device__ __forceinline__ unsigned long long* ctr_at(uint64_t* ctr, uint32_t k) {
   return reinterpret_cast<unsigned long long*>(ctr + k * kCtrSpread);
@@ -436,6 +436,13 @@ struct GenArgs {
   uint64_t dead_cap;
   uint64_t* ctr;  // kCtrCount counters, kCtrSpread words apart (see ctr_at)
   uint32_t dedup;
+  // Successor counts alternate between kCtrSucc and kCtrSuccAlt from slice
+  // to slice: this slice reserves room on succ_ctr, and the kernel's first
+  // thread zeroes the other one for the next slice (the previous slice's
+  // append kernel, its last reader, has finished) and, with reset_tail, the
+  // next-frontier tail at the first slice of a level.  No host-side clears.
+  uint32_t succ_ctr;
+  uint32_t reset_tail;
 };
 
 // Load, count and deadlock-check this lane's frontier state.
@@ -480,7 +487,7 @@ __device__ inline void gen_wave_filtered(const GenArgs& a, const uint32_t* img, 
     const uint32_t n_keep = n_st - wd;
     unsigned long long base = 0;
     if (lane == 0 && n_keep)
-      base = atomicAdd(ctr_at(a.ctr, kCtrSucc), static_cast<unsigned long long>(n_keep));
+      base = atomicAdd(ctr_at(a.ctr, a.succ_ctr), static_cast<unsigned long long>(n_keep));
     base = __shfl(base, 0, 64);
     if (base + n_keep > a.succ_cap) {
       // cannot happen with the host's bound; refuse rather than overrun
@@ -512,6 +519,10 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   __shared__ uint32_t wave_total[4];
   __shared__ unsigned long long group_base;
   uint32_t* img = smem;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *ctr_at(a.ctr, a.succ_ctr == kCtrSucc ? kCtrSuccAlt : kCtrSucc) = 0;
+    if (a.reset_tail) *ctr_at(a.ctr, kCtrTail) = 0;
+  }
   for (uint32_t k = threadIdx.x; k < a.img_words; k += 256) img[k] = a.img[k];
   __syncthreads();
   const int wave = static_cast<int>(threadIdx.x >> 6);
@@ -538,7 +549,7 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
                        wave_total[3];
     unsigned long long b = 0;
     if (t) {
-      b = atomicAdd(ctr_at(a.ctr, kCtrSucc), static_cast<unsigned long long>(t));
+      b = atomicAdd(ctr_at(a.ctr, a.succ_ctr), static_cast<unsigned long long>(t));
       atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(t));
       if (b + t > a.succ_cap) {
         // cannot happen with the host's bound; refuse rather than overrun
