@@ -391,6 +391,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   }
   constexpr size_t kCtrWords = gx::kCtrCount * gx::kCtrSpread;
   if (!eb.ctr && (hipMalloc(&eb.ctr, kCtrWords * sizeof(uint64_t)) != hipSuccess ||
+                  hipHostMalloc(&eb.ctr_host, kCtrWords * sizeof(uint64_t)) != hipSuccess ||
                   hipMalloc(&eb.status, 8) != hipSuccess ||
                   hipMalloc(&eb.key, 4 * sizeof(uint32_t)) != hipSuccess)) {
     (void)hipGetLastError();
@@ -402,8 +403,10 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
 
   uint32_t init[4] = {0, 0, 0, 0};
   gx::pack_host(ni, ni.initial.data(), init);
-  uint64_t ctr_raw[kCtrWords] = {};
-  // the level's counters, spread over cache lines on the device
+  // the level's counters, spread over cache lines on the device, read back
+  // into pinned host memory
+  uint64_t* ctr_raw = eb.ctr_host;
+  std::memset(ctr_raw, 0, kCtrWords * sizeof(uint64_t));
   auto ctr = [&](uint32_t k) { return ctr_raw[k * gx::kCtrSpread]; };
   if (hipMemcpyAsync(eb.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
                      stream) != hipSuccess ||
@@ -483,7 +486,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
   auto read_ctr = [&]() -> gx_status {
-    if (hipMemcpyAsync(ctr_raw, eb.ctr, sizeof(ctr_raw), hipMemcpyDeviceToHost, stream) !=
+    if (hipMemcpyAsync(ctr_raw, eb.ctr, kCtrWords * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                       stream) !=
             hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return GX_EDEVICE;

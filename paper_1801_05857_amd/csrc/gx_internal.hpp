@@ -20,6 +20,7 @@ struct gx_explore_buffers {
   uint32_t* succ = nullptr;  // successors of a level slice, before the table probe
   uint64_t succ_cap = 0;     // states
   uint64_t* ctr = nullptr;  // level counters, one cache line each
+  uint64_t* ctr_host = nullptr;  // pinned host copy of ctr (per-level read-back)
   uint8_t* status = nullptr;
   uint32_t* key = nullptr;  // 4 words
   // safety monitor: bad-state bitmask, violating states, their running count

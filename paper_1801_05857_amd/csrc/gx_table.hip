@@ -120,6 +120,7 @@ void free_table(gx_table* t) {
                   static_cast<void*>(e.key), static_cast<void*>(e.mon),
                   static_cast<void*>(e.viol), static_cast<void*>(e.viol_ctr)})
     if (p) (void)hipFree(p);
+  if (e.ctr_host) (void)hipHostFree(e.ctr_host);
   delete t;
 }
 
