@@ -85,6 +85,34 @@ def algorithmic_bytes_per_op(w: int, B: int, probes_per_op: float, new_frac: flo
     return 4 * w + 1 + probes_per_op * max(4 * B, GRANULE) + new_frac * GRANULE
 
 
+def run_fop_sub_batches(gx, torch, keys, n_distinct, B, G, U, alpha, H, sub):
+    """The same insertion into a cleared table as back-to-back launches of
+    `sub` keys each on one stream (fastest of two runs after a warm-up):
+    returns (ms, NEW count, FULL count)."""
+    n = keys.shape[0]
+    cap = int(n_distinct / alpha + 0.999999)
+    t = gx.Table(2, B, cap, subgroup=G, keys_per_subgroup=U, max_hashes=H)
+    st = torch.empty(n, dtype=torch.uint8, device=keys.device)
+    stream = torch.cuda.current_stream()
+    best = None
+    for rep in range(3):
+        t.clear(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for lo in range(0, n, sub):
+            t.find_or_put(keys[lo:lo + sub], st[lo:lo + sub], None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+    new = int((st == gx.GX_NEW).sum().item())
+    full = int((st == gx.GX_FULL).sum().item())
+    t.close()
+    return best, new, full
+
+
 def run_fop(gx, torch, keys, n_distinct, B, G, U, alpha, H, steps, warmup):
     """Time `steps` steps of (clear, find-or-put); returns a dict of figures."""
     n = keys.shape[0]
@@ -704,6 +732,13 @@ def main():
     out["roofline"]["random_read_ceiling"] = {
         "granule_bytes": max(4 * args.bucket, GRANULE), "G_reads_per_s": round(ceil / 1e9, 2),
         "probes_per_s_frac": round(n * r["probes_per_op"] / (r["fop_ms"] * 1e-3) / ceil, 4)}
+    # the same keys as 2^20-key launches back to back (one batch vs sub-batches)
+    sub_ms, sub_new, sub_full = run_fop_sub_batches(gx, torch, keys, n_distinct, args.bucket,
+                                                    args.subgroup, args.kps, args.alpha, H,
+                                                    1 << 20)
+    out["sub_batches_2p20"] = {"launches": (n + (1 << 20) - 1) >> 20,
+                               "Mops_per_s": round(n / (sub_ms * 1e-3) / 1e6, 1),
+                               "new": sub_new, "full": sub_full}
     if args.alpha == 0.5 and not args.no_alpha9:
         r9 = run_fop(gx, torch, keys, n_distinct, args.bucket, args.subgroup, args.kps, 0.9, 128,
                      2, 1)

@@ -445,6 +445,7 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
       in.t.c0 = hc[1];
       in.t.H = b->H;
       in.t.counters = c.stats;
+      in.t.ctr_slots = 1;  // the batch kernels keep no statistics
       in.img_off = static_cast<uint32_t>(img_off[k]);
       in.img_words = static_cast<uint32_t>(imgs[i].size());
       const uint64_t fcap = gx::align_up(opts->capacity[i] * S, 64);

@@ -96,6 +96,12 @@ enum Counter : int {
   kNumCounters = 8
 };
 
+// Statistics counter sets per table: workgroups add to set blockIdx % sets,
+// so the adds at the end of a launch spread over many cache lines instead
+// of all meeting on one (a launch of 2^20 keys spent most of its time
+// there); readers sum the sets.
+constexpr uint32_t kCtrSets = 2048;
+
 struct TableDev {
   uint32_t* words;
   uint64_t n_buckets;
@@ -103,7 +109,8 @@ struct TableDev {
   uint64_t seed;
   uint64_t a0, c0;     // first constant set, passed by value
   uint32_t H;
-  uint64_t* counters;  // kNumCounters
+  uint64_t* counters;  // ctr_slots sets of kNumCounters words
+  uint32_t ctr_slots = 1;  // workgroup b adds its statistics to set b % ctr_slots
 };
 
 // A value every lane of the wavefront holds the same copy of, moved to a
@@ -130,6 +137,7 @@ __device__ __forceinline__ TableDev uniform_table(const TableDev& t) {
   u.c0 = uniform64(t.c0);
   u.H = uniform32(t.H);
   u.counters = uniform_ptr(t.counters);
+  u.ctr_slots = uniform32(t.ctr_slots);
   return u;
 }
 
@@ -307,16 +315,17 @@ __device__ inline void flush_stats(const TableDev& t, const LaneStats& st, uint6
   const uint32_t stored = st.stored, lookups = st.lookups, full = st.full, invalid = st.invalid;
   const uint32_t probes = wave_sum(st.probes);
   const uint32_t mj = wave_max(st.max_j);
+  uint64_t* c = t.counters + static_cast<uint64_t>(blockIdx.x % t.ctr_slots) * kNumCounters;
   if (__lane_id() == 0) {
     if (stored) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntStored]), stored);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntStored]), stored);
       if (n_new) atomicAdd(reinterpret_cast<unsigned long long*>(n_new), stored);
     }
-    if (lookups) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntLookups]), lookups);
-    if (probes) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntProbes]), probes);
-    if (full) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntFull]), full);
-    if (invalid) atomicAdd(reinterpret_cast<unsigned long long*>(&t.counters[kCntInvalid]), invalid);
-    if (mj) atomicMax(reinterpret_cast<unsigned long long*>(&t.counters[kCntMaxJ]), mj);
+    if (lookups) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntLookups]), lookups);
+    if (probes) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntProbes]), probes);
+    if (full) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntFull]), full);
+    if (invalid) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntInvalid]), invalid);
+    if (mj) atomicMax(reinterpret_cast<unsigned long long*>(&c[kCntMaxJ]), mj);
   }
 }
 

@@ -43,7 +43,8 @@ struct gx_table {
   uint64_t n_buckets = 0;
   uint32_t* words = nullptr;     // n_buckets * B
   uint64_t* hc = nullptr;        // 2*H hash constants
-  uint64_t* counters = nullptr;  // gx::kNumCounters
+  uint64_t* counters = nullptr;  // ctr_slots sets of gx::kNumCounters
+  uint32_t ctr_slots = 1;
   uint64_t a0 = 0, c0 = 0;
   gx_explore_buffers eb;
 
@@ -57,6 +58,7 @@ struct gx_table {
     t.c0 = c0;
     t.H = H;
     t.counters = counters;
+    t.ctr_slots = ctr_slots;
     return t;
   }
 };

@@ -16,14 +16,17 @@ namespace gx {
 
 // ------------------------------------------------------------------ kernels
 __global__ __launch_bounds__(256) void fill_kernel(uint4* p, uint64_t n16, uint32_t value,
-                                                   uint64_t* counters) {
+                                                   uint64_t* counters, uint32_t n_counters) {
   const uint4 e = make_uint4(value, value, value, value);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
        i += stride) {
     p[i] = e;
   }
-  if (counters && blockIdx.x == 0 && threadIdx.x < kNumCounters) counters[threadIdx.x] = 0;
+  if (counters)
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_counters;
+         i += stride)
+      counters[i] = 0;
 }
 
 // Random-access probe: subgroups of LANES lanes read LANES*4 contiguous bytes
@@ -88,7 +91,7 @@ hipError_t fill_words(uint32_t* p, uint64_t n_words, uint32_t value, int device,
   const uint32_t grid = static_cast<uint32_t>(
       std::max<uint64_t>(1, std::min<uint64_t>(want, resident_grid(device, 8))));
   hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream, reinterpret_cast<uint4*>(p),
-                     n16, value, static_cast<uint64_t*>(nullptr));
+                     n16, value, static_cast<uint64_t*>(nullptr), 0u);
   return hipGetLastError();
 }
 
@@ -100,7 +103,8 @@ hipError_t clear_storage(const gx_table* t, hipStream_t stream) {
   const uint32_t grid =
       static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(want, resident_grid(t->device, 8))));
   hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, stream,
-                     reinterpret_cast<uint4*>(t->words), n16, kEmpty, t->counters);
+                     reinterpret_cast<uint4*>(t->words), n16, kEmpty, t->counters,
+                     t->ctr_slots * kNumCounters);
   return hipGetLastError();
 }
 
@@ -178,11 +182,13 @@ gx_status gx_table_create(uint32_t w, uint32_t B, uint64_t capacity, const gx_ta
   t->c0 = hc[1];
   if (hipMalloc(&t->words, n_buckets * B * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&t->hc, hc.size() * sizeof(uint64_t)) != hipSuccess ||
-      hipMalloc(&t->counters, gx::kNumCounters * sizeof(uint64_t)) != hipSuccess) {
+      hipMalloc(&t->counters, uint64_t(gx::kCtrSets) * gx::kNumCounters * sizeof(uint64_t)) !=
+          hipSuccess) {
     (void)hipGetLastError();
     gx::free_table(t);
     return GX_ENOMEM;
   }
+  t->ctr_slots = gx::kCtrSets;
   if (hipMemcpy(t->hc, hc.data(), hc.size() * sizeof(uint64_t), hipMemcpyHostToDevice) !=
           hipSuccess ||
       gx::clear_storage(t, nullptr) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
@@ -237,10 +243,17 @@ gx_status gx_table_get_info(const gx_table* t, gx_table_info* out) {
 
 gx_status gx_table_stats(gx_table* t, gx_stats* out) {
   if (!t || !out) return GX_EINVAL;
-  uint64_t c[gx::kNumCounters];
+  std::vector<uint64_t> sets(static_cast<size_t>(t->ctr_slots) * gx::kNumCounters);
   if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(c, t->counters, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(sets.data(), t->counters, sets.size() * sizeof(uint64_t),
+                hipMemcpyDeviceToHost) != hipSuccess)
     return GX_EDEVICE;
+  uint64_t c[gx::kNumCounters] = {};
+  for (uint32_t b = 0; b < t->ctr_slots; ++b)
+    for (int k = 0; k < gx::kNumCounters; ++k) {
+      const uint64_t v = sets[static_cast<size_t>(b) * gx::kNumCounters + k];
+      c[k] = k == gx::kCntMaxJ ? std::max(c[k], v) : c[k] + v;
+    }
   out->stored = c[gx::kCntStored];
   out->lookups = c[gx::kCntLookups];
   out->probes = c[gx::kCntProbes];
