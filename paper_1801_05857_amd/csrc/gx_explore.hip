@@ -477,6 +477,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   ap.keys = nullptr;
   ap.n_keys = nullptr;  // per slice: the successor counter its generation uses
   ap.ctr = eb.ctr;
+  ap.count_trans = g.dedup ? 0u : 1u;  // the filtered generation counts its own
   const uint32_t dedup_words =
       g.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
                                                                : gx::dedup_entries<4>())

@@ -549,8 +549,9 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
                        wave_total[3];
     unsigned long long b = 0;
     if (t) {
+      // (the slice's transition count is its successor count: the append
+      // kernel adds it once)
       b = atomicAdd(ctr_at(a.ctr, a.succ_ctr), static_cast<unsigned long long>(t));
-      atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(t));
       if (b + t > a.succ_cap) {
         // cannot happen with the host's bound; refuse rather than overrun
         atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagFrontierOverflow);
@@ -574,6 +575,7 @@ struct AppendArgs {
   uint32_t* frontier_out;
   uint64_t cap_out;        // states
   uint64_t* ctr;           // the level's counters (see ctr_at)
+  uint32_t count_trans;    // add n_keys to the transition count (unfiltered slices)
 };
 
 constexpr uint32_t kAppendKeys = 256;  // NEW keys a wavefront gathers in LDS
@@ -604,6 +606,8 @@ __global__ __launch_bounds__(256) void append_kernel(AppendArgs a) {
   const int lane = __lane_id();
   // a generation that overran the buffer has flagged it; never read past it
   const uint64_t n = min(*a.n_keys, a.keys_cap);
+  if (a.count_trans && blockIdx.x == 0 && threadIdx.x == 0 && n)
+    atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(n));
   const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
   LaneStats st;
