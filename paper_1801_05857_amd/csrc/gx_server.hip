@@ -117,6 +117,8 @@ struct gx_server {
   gx::ServeJob* d_jobs = nullptr;
   uint32_t* d_img = nullptr;
   uint64_t* d_ctr = nullptr;
+  uint64_t* h_ctr = nullptr;   // pinned host copy of d_ctr (per-step read-back)
+  gx::ServeJob* h_jobs = nullptr;  // pinned staging of the step's job descriptors
   std::thread th;
 };
 
@@ -303,8 +305,7 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
 }
 
 void step_loop(gx_server* s) {
-  std::vector<ServeJob> hjs[3];  // per slot-width class; alive until the step's sync
-  std::vector<uint64_t> ctr;
+  std::vector<ServeJob> hjs[3];  // per slot-width class
   while (true) {
     {
       std::unique_lock<std::mutex> lock(s->mu);
@@ -350,7 +351,11 @@ void step_loop(gx_server* s) {
       a.img = s->d_img;
       a.img_stride = (img_max + 3) & ~3u;
       const size_t lds = (a.img_stride + kStageWords) * sizeof(uint32_t);
-      hipError_t e = hipMemcpyAsync(const_cast<ServeJob*>(a.jobs), hj.data(),
+      // staged in pinned memory (one region per class, reused only after the
+      // step's synchronisation) so the upload is a plain asynchronous copy
+      ServeJob* staged = s->h_jobs + (S == 1 ? 0 : S == 2 ? 1 : 2) * s->max_active;
+      std::copy(hj.begin(), hj.end(), staged);
+      hipError_t e = hipMemcpyAsync(const_cast<ServeJob*>(a.jobs), staged,
                                     hj.size() * sizeof(ServeJob), hipMemcpyHostToDevice, s->stream);
       if (e == hipSuccess) {
         switch (S) {
@@ -361,14 +366,16 @@ void step_loop(gx_server* s) {
       }
       if (e != hipSuccess) ok = false;
     }
-    // one synchronisation per step: the classes' launches follow each other
-    // on the stream without host round trips (the host copies in hjs stay
-    // alive until here)
-    if (hipStreamSynchronize(s->stream) != hipSuccess) ok = false;
-    ctr.assign(kSlotCtrWords * static_cast<size_t>(s->max_active), 0);
-    if (ok && hipMemcpy(ctr.data(), s->d_ctr, ctr.size() * sizeof(uint64_t),
-                        hipMemcpyDeviceToHost) != hipSuccess)
+    // one synchronisation per step: the classes' launches and the read-back
+    // of the counters of slots 0 .. the highest active one follow each other
+    // on the stream without host round trips
+    uint32_t n_slots = 0;
+    for (const auto& j : s->active) n_slots = std::max(n_slots, j.slot + 1);
+    if (hipMemcpyAsync(s->h_ctr, s->d_ctr, kSlotCtrWords * n_slots * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
       ok = false;
+    const uint64_t* ctr = s->h_ctr;
     std::lock_guard<std::mutex> lock(s->mu);
     ++s->stats.steps;
     for (size_t k = s->active.size(); k-- > 0;) {
@@ -389,10 +396,15 @@ void step_loop(gx_server* s) {
         j.levels.push_back(n_next);
         j.n_in = n_next;
         j.cur ^= 1;
-        if (hipMemsetAsync(s->d_ctr + kSlotCtrWords * j.slot + kCtrTail * kCtrSpread, 0,
-                           sizeof(uint64_t), s->stream) != hipSuccess)
-          finish_job(s, k, GX_EDEVICE, 0, 0);
       }
+    }
+    // clear the next-frontier tails of slots 0 .. n_slots - 1 in one strided
+    // fill (finished or idle slots included: admission clears a slot's
+    // counters anyway)
+    if (ok && n_slots &&
+        hipMemset2DAsync(s->d_ctr + kCtrTail * kCtrSpread, kSlotCtrWords * sizeof(uint64_t), 0,
+                         sizeof(uint64_t), n_slots, s->stream) != hipSuccess) {
+      for (size_t k = s->active.size(); k-- > 0;) finish_job(s, k, GX_EDEVICE, 0, 0);
     }
     s->cv_done.notify_all();
   }
@@ -414,6 +426,8 @@ void destroy_server(gx_server* s) {
   if (s->d_jobs) (void)hipFree(s->d_jobs);
   if (s->d_img) (void)hipFree(s->d_img);
   if (s->d_ctr) (void)hipFree(s->d_ctr);
+  if (s->h_ctr) (void)hipHostFree(s->h_ctr);
+  if (s->h_jobs) (void)hipHostFree(s->h_jobs);
   if (s->arena) (void)hipFree(s->arena);
   if (s->d_hc) (void)hipFree(s->d_hc);
   if (s->d_small) (void)hipFree(s->d_small);
@@ -481,7 +495,10 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
       hipMalloc(&s->d_jobs, 3ull * s->max_active * sizeof(gx::ServeJob)) != hipSuccess ||
       hipMalloc(&s->d_img, static_cast<uint64_t>(s->max_active) * gx::kImgMaxWords *
                                sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&s->d_ctr, gx::kSlotCtrWords * s->max_active * sizeof(uint64_t)) != hipSuccess) {
+      hipMalloc(&s->d_ctr, gx::kSlotCtrWords * s->max_active * sizeof(uint64_t)) != hipSuccess ||
+      hipHostMalloc(&s->h_ctr, gx::kSlotCtrWords * s->max_active * sizeof(uint64_t)) !=
+          hipSuccess ||
+      hipHostMalloc(&s->h_jobs, 3ull * s->max_active * sizeof(gx::ServeJob)) != hipSuccess) {
     (void)hipGetLastError();
     gx::destroy_server(s);
     return GX_ENOMEM;
