@@ -315,18 +315,16 @@ __device__ inline void flush_stats(const TableDev& t, const LaneStats& st, uint6
   const uint32_t stored = st.stored, lookups = st.lookups, full = st.full, invalid = st.invalid;
   const uint32_t probes = wave_sum(st.probes);
   const uint32_t mj = wave_max(st.max_j);
+  if (__lane_id() != 0) return;
+  if (stored && n_new) atomicAdd(reinterpret_cast<unsigned long long*>(n_new), stored);
+  if (t.counters == nullptr) return;  // a table that keeps no statistics
   uint64_t* c = t.counters + static_cast<uint64_t>(blockIdx.x % t.ctr_slots) * kNumCounters;
-  if (__lane_id() == 0) {
-    if (stored) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntStored]), stored);
-      if (n_new) atomicAdd(reinterpret_cast<unsigned long long*>(n_new), stored);
-    }
-    if (lookups) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntLookups]), lookups);
-    if (probes) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntProbes]), probes);
-    if (full) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntFull]), full);
-    if (invalid) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntInvalid]), invalid);
-    if (mj) atomicMax(reinterpret_cast<unsigned long long*>(&c[kCntMaxJ]), mj);
-  }
+  if (stored) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntStored]), stored);
+  if (lookups) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntLookups]), lookups);
+  if (probes) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntProbes]), probes);
+  if (full) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntFull]), full);
+  if (invalid) atomicAdd(reinterpret_cast<unsigned long long*>(&c[kCntInvalid]), invalid);
+  if (mj) atomicMax(reinterpret_cast<unsigned long long*>(&c[kCntMaxJ]), mj);
 }
 
 // Find-or-put of U keys per subgroup.  Every lane of a subgroup holds the same

@@ -167,7 +167,7 @@ gx_table* job_table(gx_server* s, uint32_t w, uint64_t slots, uint64_t off, uint
   char* small = s->d_small + static_cast<uint64_t>(slot) * kSlotSmallBytes;
   t->words = reinterpret_cast<uint32_t*>(base);
   t->hc = s->d_hc;
-  t->counters = reinterpret_cast<uint64_t*>(small);  // one set of kNumCounters words
+  t->counters = nullptr;  // job tables keep no statistics
   t->ctr_slots = 1;
   t->eb.key = reinterpret_cast<uint32_t*>(small + 64);
   t->eb.status = reinterpret_cast<uint8_t*>(small + 96);
