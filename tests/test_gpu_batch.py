@@ -64,6 +64,14 @@ def test_batch_matches_oracle(dev, mixed, use_graph):
         _check(b.results(), want)
 
 
+def test_batch_degenerate_networks(dev):
+    """One-state processes, no transitions, a rule that never fires, zero rules."""
+    nets = list(W.degenerate_networks().values())
+    nets += [W.independent_cycles((3, 5)), W.fig1_producer_consumers()]
+    want = [oracle.explore(n) for n in nets]
+    _check(gx.explore_batch(nets, [64] * len(nets), max_hashes=32), want)
+
+
 @pytest.mark.parametrize("B,G,U", [(8, 8, 1), (16, 16, 2), (64, 8, 2), (32, 16, 1),
                                    (8, 4, 2), (16, 4, 1), (32, 4, 2)])
 def test_batch_explicit_configurations(dev, mixed, B, G, U):

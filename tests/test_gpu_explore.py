@@ -58,6 +58,12 @@ def test_token_ring(dev, n):
     assert got.n_states == 2 * n * 3 ** (n - 1)
 
 
+@pytest.mark.parametrize("name", ["lone", "selfloop", "ones", "never", "chain"])
+@pytest.mark.parametrize("B,G", [(4, 4), (32, 8)])
+def test_degenerate_networks(dev, name, B, G):
+    _explore_and_compare(W.degenerate_networks()[name], B=B, G=G)
+
+
 @pytest.mark.parametrize("sizes", [(8, 8, 8, 8), (3, 5, 7, 11, 13), (2,) * 20, (64, 64, 64)])
 def test_independent_cycles(dev, sizes):
     _explore_and_compare(W.independent_cycles(sizes), B=16)

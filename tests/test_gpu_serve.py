@@ -35,6 +35,7 @@ def _nets():
              W.random_lts(404, 16, 64, 2, 3, 32, 0.25, 0.0)]
     nets += [W.random_lts(s, 3 + s % 3, 8, 6, 2, 8, 0.5, 0.4) for s in (2, 8, 13, 14, 24)]
     nets.append(W.wide_rule(5, 4))  # one state with 1024 successors, all deadlocks
+    nets += list(W.degenerate_networks().values())  # one-state processes, no transitions
     return nets
 
 

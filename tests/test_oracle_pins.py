@@ -296,3 +296,27 @@ def test_wide_rule_closed_form(P, k):
     assert r.n_transitions == k ** P
     assert r.levels.tolist() == [1, k ** P]
     assert len(r.deadlocks) == k ** P
+
+
+# (n_states, levels, transitions, deadlocks), each derived by hand from the
+# synchronous product's definition (Sec. 3)
+DEGENERATE = {
+    "lone": (1, [1], 0, 1),      # no transition at all: the initial state is stuck
+    "selfloop": (1, [1], 1, 0),  # the loop is a transition back to the same state
+    "ones": (1, [1], 0, 1),
+    "never": (1, [1], 0, 1),     # a label named in a rule never fires alone
+    "chain": (3, [1, 1, 1], 5, 0),  # 3 self-loops + 2 chain steps; loops prevent deadlock
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_degenerate_networks(name):
+    net = W.degenerate_networks()[name]
+    n, levels, trans, dead = DEGENERATE[name]
+    r = oracle.explore(net)
+    assert r.n_states == n
+    assert r.levels.tolist() == levels
+    assert r.n_transitions == trans
+    assert len(r.deadlocks) == dead
+    if dead:
+        assert r.deadlocks.tolist() == [[0] * r.words]  # the all-initial vector packs to 0

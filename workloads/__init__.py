@@ -193,6 +193,28 @@ def wide_rule(n_procs: int = 6, k: int = 5) -> Network:
     return _net([k + 1] * n_procs, [0] * n_procs, trans, 1, rules, f"wide_rule_{n_procs}x{k}")
 
 
+def degenerate_networks() -> dict:
+    """Edge cases of the product semantics (Sec. 3), by name.
+
+    lone      one process with one state and no transitions
+    selfloop  one process with one state and a tau self-loop
+    ones      five one-state processes, no transitions
+    never     two processes whose only rule is never enabled: process 0 offers
+              its label only in state 0, process 1 only in state 1
+    chain     a self-looping one-state process, a tau chain 0 -> 1 -> 2 and a
+              transition-less one-state process
+    """
+    empty_rules = lambda P: np.zeros((0, P), dtype=np.int32)
+    return {
+        "lone": _net([1], [0], [[]], 1, empty_rules(1), "lone"),
+        "selfloop": _net([1], [0], [[(0, 0, 0)]], 1, empty_rules(1), "selfloop"),
+        "ones": _net([1] * 5, [0] * 5, [[]] * 5, 1, empty_rules(5), "ones"),
+        "never": _net([2, 2], [0, 0], [[(0, 1, 1)], [(1, 1, 0)]], 2, [[1, 1]], "never"),
+        "chain": _net([1, 3, 1], [0, 0, 0], [[(0, 0, 0)], [(0, 0, 1), (1, 0, 2)], []], 1,
+                      empty_rules(3), "chain"),
+    }
+
+
 def random_monitor(seed: int, actions, n_states: int = 4, n_observed: int = 4):
     """A seeded deterministic automaton over ``n_observed`` of the given action
     names (a negated safety property to add to a network): states 0 ..
