@@ -551,7 +551,7 @@ def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0), relative="alo
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "gx runs on one GPU; sharding across GPUs is not implemented, so --gpus must be 1"}))
         sys.exit(2)
     import torch
 
