@@ -201,3 +201,15 @@ def test_server_arguments_rejected(lib):
     rid = ctypes.c_uint64()
     assert lib.gx_server_submit(None, None, 10, ctypes.byref(rid)) == gx.GX_EINVAL
     assert lib.gx_server_destroy(None) == gx.GX_OK
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with status 2 and
+    a JSON error line, before any device is touched."""
+    import json
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "--gpus must be 1" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
