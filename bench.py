@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -265,28 +267,43 @@ def cpu_explore_baseline(W):
 
 
 def explore_bytes_per_state(f: float, B: int, S: int) -> float:
-    """Algorithmic HBM bytes per explored state of the two-kernel level: f
-    successors each probe one bucket (at least a 64-byte granule) and pass
-    through the successor buffer (written and read, 4S bytes each way); the
-    state is read from the frontier and written to the next one (4S each);
-    its claim writes back one granule."""
-    return f * (max(4 * B, GRANULE) + 2 * 4 * S) + 2 * 4 * S + GRANULE
+    """Algorithmic HBM bytes per explored state: its f successors each probe
+    one bucket (at least a 64-byte granule), the state is read from its
+    frontier and written to the next one (4S bytes each way), and its claim
+    writes back one granule."""
+    return f * max(4 * B, GRANULE) + 2 * 4 * S + GRANULE
 
 
-def run_explore_leg(gx, torch, W, live=8, B=0, G=0, U=1, slots=None):
+def successor_buffer_bytes_per_state(f: float, S: int) -> float:
+    """HBM bytes per explored state that the two-kernel level adds on top of
+    the algorithmic ones: every successor is written to the successor buffer
+    and read back by the probe kernel (4S bytes each way).  Overhead of this
+    implementation, not counted in the roofline."""
+    return f * 2 * 4 * S
+
+
+def roofline_of(states: int, bytes_per_state_total: float, seconds: float) -> dict:
+    """Roofline fields of an exploration leg: algorithmic bytes over wall time
+    against the 8 TB/s HBM peak."""
+    gbps = bytes_per_state_total / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbps / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_state": round(bytes_per_state_total / max(1, states), 1)}
+
+
+def run_explore_leg(gx, torch, W, live=8, slots=None):
     """States explored per second on the large plain-path workload (12
     processes of 64 declared states, 3-word vectors, 3.3e9 reachable states,
-    192 GB table), with the table's buffers resident (a first exploration
-    sizes them), timed on the second exploration into the cleared table.
-    Bucket words and subgroup from the autotuner (0) unless given."""
+    192 GB table) in the table configuration W.LARGE_EXPLORE, with the
+    table's buffers resident (a first exploration sizes them), timed on the
+    second exploration into the cleared table."""
     net = W.large_random_network(live)
     w = gx.network_words(net)
     slots = slots or W.LARGE_TABLE_SLOTS
-    if not B or not G:
-        tb, tg, _ = gx.autotune(w, 0.3)
-        B, G = B or tb, G or tg
+    cfg = dict(W.LARGE_EXPLORE)
+    B = cfg.pop("bucket_words")
     torch.cuda.empty_cache()
-    t = gx.Table(w, B, slots, subgroup=G, keys_per_subgroup=U, max_hashes=16)
+    t = gx.Table(w, B, slots, **cfg)
     t0 = time.perf_counter()
     gx.explore(net, t)
     cold = time.perf_counter() - t0
@@ -298,22 +315,24 @@ def run_explore_leg(gx, torch, W, live=8, B=0, G=0, U=1, slots=None):
     st = t.stats()
     info = t.info
     f = r.n_transitions / r.n_states
-    bps = explore_bytes_per_state(f, B, info.slot_words)
+    S = info.slot_words
+    bps = explore_bytes_per_state(f, B, S)
     t.close()
-    return {"workload": (f"random network: 12 processes x 64 declared states ({live} live), "
-                         f"out-degree 3, 32 labels, 25% rendezvous, seed 1, sink 0.15; "
-                         f"{w}-word vectors; table {info.n_slots} slots ({info.bytes / 1e9:.0f} GB), "
-                         f"buckets of {B} words and subgroup {G} (autotuned), {U} key(s) in flight"),
-            "states": r.n_states, "transitions": r.n_transitions, "levels": len(r.levels),
-            "seconds": round(dt, 4), "cold_seconds": round(cold, 4),
-            "states_per_s": round(r.n_states / dt),
-            "lookups_per_s": round(r.n_transitions / dt),
-            "successors_per_state": round(f, 2),
-            "probes_per_lookup": round(st.probes / max(1, st.lookups), 4),
-            "load_factor": round(r.n_states / info.n_slots, 3),
-            "algorithmic_bytes_per_state": round(bps, 1),
-            "algorithmic_GBps": round(r.n_states * bps / dt / 1e9, 1),
-            "roofline_frac": round(r.n_states * bps / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    out = {"workload": (f"random network: 12 processes x 64 declared states ({live} live), "
+                        f"out-degree 3, 32 labels, 25% rendezvous, seed 1, sink 0.15; "
+                        f"{w}-word vectors; table {info.n_slots} slots "
+                        f"({info.bytes / 1e9:.0f} GB), buckets of {B} words, subgroup "
+                        f"{cfg['subgroup']}, {cfg['keys_per_subgroup']} key(s) in flight"),
+           "states": r.n_states, "transitions": r.n_transitions, "levels": len(r.levels),
+           "seconds": round(dt, 4), "cold_seconds": round(cold, 4),
+           "states_per_s": round(r.n_states / dt),
+           "lookups_per_s": round(r.n_transitions / dt),
+           "successors_per_state": round(f, 2),
+           "probes_per_lookup": round(st.probes / max(1, st.lookups), 4),
+           "load_factor": round(r.n_states / info.n_slots, 3),
+           "roofline": roofline_of(r.n_states, r.n_states * bps, dt),
+           "successor_buffer_bytes_per_state": round(successor_buffer_bytes_per_state(f, S), 1)}
+    return out
 
 
 def run_dup_sweep(gx, torch, W, log2n=27, alpha=0.5):
@@ -397,6 +416,10 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
     states = sum(r.n_states for r in ok)
     trans = sum(r.n_transitions for r in ok)
     t_batch = sorted(runs)[len(runs) // 2]
+    algo_bytes = sum(r.n_states * explore_bytes_per_state(r.n_transitions / max(1, r.n_states),
+                                                          cfg[0], 4 if r.words_per_state == 3
+                                                          else r.words_per_state)
+                     for (st, r), cfg in zip(res, cfgs) if st == gx.GX_OK)
     # one exploration per instance, tables and buffers resident
     tables = [gx.Table(gx.network_words(nt), B, c, subgroup=G, keys_per_subgroup=U,
                        max_hashes=hashes) for nt, c, (B, G, U) in zip(nets, caps, cfgs)]
@@ -419,7 +442,9 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
             continue
         single_states += r.n_states
         st, rb = res[k]
-        if st != gx.GX_OK or rb.n_states != r.n_states or rb.levels.tolist() != r.levels.tolist():
+        if (st != gx.GX_OK or rb.n_states != r.n_states or rb.levels.tolist() != r.levels.tolist()
+                or rb.n_transitions != r.n_transitions
+                or not np.array_equal(rb.deadlocks, r.deadlocks)):
             mismatch += 1
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
@@ -432,6 +457,7 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
                     "kernel class from a hipGraph",
         "instances": n, "ok": len(ok), "states": states, "transitions": trans,
         "seconds": round(t_batch, 4), "states_per_s": round(states / t_batch),
+        "roofline": roofline_of(states, algo_bytes, t_batch),
         "one_launch_per_instance_seconds": round(t_single, 4),
         "one_launch_per_instance_states_per_s": round(single_states / t_single),
         "speedup_vs_one_launch_per_instance": round(t_single / t_batch, 2),

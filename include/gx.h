@@ -160,6 +160,14 @@ gx_status gx_table_dump(gx_table* table, uint32_t* host_keys, uint64_t cap_state
 gx_status gx_table_read_raw(gx_table* table, uint32_t* host_words, uint64_t first_word,
                             uint64_t n_words);
 
+/* Copy raw bucket storage words [first_word, first_word + n_words) into device
+ * memory dev_words (caller-owned, on the table's device), e.g. to inspect a
+ * table too large for host memory window by window.  Stream-ordered on
+ * hip_stream.  Errors: GX_EINVAL (null pointer with n_words > 0, range outside
+ * the storage), GX_EDEVICE (the copy could not be queued). */
+gx_status gx_table_copy_raw(gx_table* table, uint32_t* dev_words, uint64_t first_word,
+                            uint64_t n_words, void* hip_stream);
+
 /*
  * Bucket index that hash function j assigns to a key (host only).  The family
  * is h_j(k) = mulhi64(a_j * m(k) + c_j, n_buckets): m is a 64-bit mix of the

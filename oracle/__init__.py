@@ -13,6 +13,11 @@ The C++ side (``oracle.cpp``) is a plain model of what the GPU path computes:
   states (Sec. 3, Fig. 1).
 * ``bruteforce``: a dense-bitmap fixpoint over every vector of local states,
   used only to pin ``explore`` on tiny networks.
+* ``explore_dense``: the same BFS with the visited set and the levels held
+  as dense bitmaps over the product of locally reachable states and levels
+  expanded by several threads, for state spaces of billions of states; it
+  returns an order-independent ``digest`` of the reachable set instead of the
+  set itself.
 * ``pack_plan`` / ``pack``: the packing of process states into 31-bit payload
   words (Sec. 3: network data combined in 32-bit integers; Sec. 5.2: a vector
   of more than 32 bits takes several integers).
@@ -62,6 +67,23 @@ class _Result(ctypes.Structure):
     ]
 
 
+class _DenseResult(ctypes.Structure):
+    _fields_ = [
+        ("words", ctypes.c_uint32),
+        ("n_levels", ctypes.c_uint32),
+        ("n_states", ctypes.c_uint64),
+        ("n_transitions", ctypes.c_uint64),
+        ("levels", ctypes.POINTER(ctypes.c_uint64)),
+        ("n_deadlocks", ctypes.c_uint64),
+        ("n_deadlocks_listed", ctypes.c_uint64),
+        ("deadlocks", ctypes.POINTER(ctypes.c_uint32)),
+        ("digest", ctypes.c_uint64 * 2),
+        ("dead_digest", ctypes.c_uint64 * 2),
+        ("index_space", ctypes.c_uint64),
+        ("visited", ctypes.POINTER(ctypes.c_uint32)),
+    ]
+
+
 _lib = None
 
 
@@ -99,6 +121,11 @@ def _load():
         lib.oracle_successors.argtypes = net_args + [vp, u64, vp, ctypes.POINTER(vp),
                                                      ctypes.POINTER(u64)]
         lib.oracle_free.argtypes = [vp]
+        lib.oracle_digest.argtypes = [u32, vp, u64, vp]
+        lib.oracle_explore_dense.restype = i32
+        lib.oracle_explore_dense.argtypes = net_args + [u32, u64, u64, i32,
+                                                        ctypes.POINTER(_DenseResult)]
+        lib.oracle_dense_result_free.argtypes = [ctypes.POINTER(_DenseResult)]
         _lib = lib
     return _lib
 
@@ -280,4 +307,71 @@ def pack(n_states, local) -> np.ndarray:
     out = np.zeros((loc.shape[0], words), dtype=np.uint32)
     if _load().oracle_pack(ns.shape[0], _ptr(ns), _ptr(loc), loc.shape[0], _ptr(out)) != 0:
         raise ValueError("invalid process sizes")
+    return out
+
+
+def digest(states, words: int | None = None) -> tuple[int, int]:
+    """Order-independent digest of a set of packed states (n x words): two
+    sums modulo 2^31 - 1 of a cubic of a fixed linear form of the words.  Test
+    bookkeeping for comparing sets too large to list, not part of the method."""
+    st = np.ascontiguousarray(states, dtype=np.uint32)
+    if words is None:
+        words = st.shape[1] if st.ndim == 2 else 1
+    st = st.reshape(-1, words)
+    out = np.zeros(2, dtype=np.uint64)
+    _load().oracle_digest(words, _ptr(st), st.shape[0], _ptr(out))
+    return int(out[0]), int(out[1])
+
+
+@dataclass
+class DenseResult:
+    words: int
+    n_states: int
+    n_transitions: int
+    levels: np.ndarray       # uint64
+    n_deadlocks: int
+    deadlocks: np.ndarray | None  # (n, words) sorted; None when above the cap
+    digest: tuple            # digest() of the reachable set
+    dead_digest: tuple       # digest() of the deadlock set
+    index_space: int         # product of the locally reachable state counts
+    visited: np.ndarray | None
+
+
+def explore_dense(net, threads: int = 0, max_index_space: int = 1 << 40,
+                  dead_cap: int = 1 << 20, want_visited: bool = False) -> DenseResult:
+    """BFS of the synchronous product (Sec. 3) over dense bitmaps, levels
+    expanded by ``threads`` threads (0: one per core).  Needs three bitmaps of
+    index_space bits.  Deadlocks are listed when there are at most
+    ``dead_cap``; the reachable set is returned as its ``digest`` (and listed
+    with want_visited)."""
+    args, keep = _flatten(net)
+    res = _DenseResult()
+    lib = _load()
+    rc = lib.oracle_explore_dense(*args, int(threads), int(max_index_space), int(dead_cap),
+                                  int(want_visited), ctypes.byref(res))
+    del keep
+    if rc == -1:
+        raise ValueError("invalid network")
+    if rc == -2:
+        raise OverflowError("product of locally reachable state counts exceeds the limit")
+    if rc == -3:
+        raise MemoryError("cannot allocate the bitmaps")
+    if rc != 0:
+        raise RuntimeError(f"dense exploration failed ({rc})")
+    w = res.words
+    levels = np.ctypeslib.as_array(res.levels, shape=(res.n_levels,)).copy()
+    dead = None
+    if res.n_deadlocks == res.n_deadlocks_listed:
+        dead = np.zeros((0, w), np.uint32)
+        if res.n_deadlocks:
+            dead = np.ctypeslib.as_array(res.deadlocks, shape=(res.n_deadlocks * w,)).copy()
+            dead = dead.reshape(-1, w)
+    vis = None
+    if want_visited:
+        vis = np.ctypeslib.as_array(res.visited, shape=(res.n_states * w,)).copy().reshape(-1, w)
+    out = DenseResult(w, int(res.n_states), int(res.n_transitions), levels,
+                      int(res.n_deadlocks), dead, (int(res.digest[0]), int(res.digest[1])),
+                      (int(res.dead_digest[0]), int(res.dead_digest[1])),
+                      int(res.index_space), vis)
+    lib.oracle_dense_result_free(ctypes.byref(res))
     return out

@@ -43,11 +43,14 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <memory>
+#include <thread>
 #include <unordered_set>
 #include <vector>
 
@@ -617,6 +620,333 @@ int oracle_bruteforce(uint32_t P, const uint32_t* n_states, const uint32_t* init
     if (want_visited) vis.push_back(v);
   }
   fill_result(plan, levels, n_reach, transitions, dead, want_visited ? &vis : nullptr, out);
+  return 0;
+}
+
+
+// ---- set digest -----------------------------------------------------------
+// Order-independent digest of a set of packed states, for comparing sets too
+// large to list (billions of states).  It is test bookkeeping, not part of the
+// method: two sums, modulo the Mersenne prime p = 2^31 - 1, of f_k = u^3 + u
+// mod p, where u = c_k + sum_i (x_i mod p) * a_k[i] mod p over the state's
+// words x_i.  The tests evaluate the same formula over a table's contents.
+namespace {
+constexpr uint64_t kDigestP = 0x7FFFFFFFULL;
+constexpr uint64_t kDigestA[2][4] = {{1103515245ULL, 1664525013ULL, 22695477ULL, 134775813ULL},
+                                     {1013904223ULL, 69069ULL, 2147483629ULL, 1566083941ULL}};
+constexpr uint64_t kDigestC[2] = {12345ULL, 987654321ULL};
+
+void digest_add(const Vec& v, uint32_t words, uint64_t* d) {
+  for (int k = 0; k < 2; ++k) {
+    uint64_t u = kDigestC[k];
+    for (uint32_t i = 0; i < words; ++i)
+      u = (u + (v[i] % kDigestP) * kDigestA[k][i] % kDigestP) % kDigestP;
+    const uint64_t f = (u * u % kDigestP * u + u) % kDigestP;
+    d[k] = (d[k] + f) % kDigestP;
+  }
+}
+}  // namespace
+
+// Digest of n packed states (n x words), written to digest[0..1].
+void oracle_digest(uint32_t words, const uint32_t* states, uint64_t n, uint64_t* digest) {
+  digest[0] = digest[1] = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    Vec v{};
+    for (uint32_t k = 0; k < words; ++k) v[k] = states[i * words + k];
+    digest_add(v, words, digest);
+  }
+}
+
+// ---- exploration over dense bitmaps ----------------------------------------
+struct oracle_dense_result {
+  uint32_t words;
+  uint32_t n_levels;
+  uint64_t n_states;
+  uint64_t n_transitions;
+  uint64_t* levels;            // n_levels
+  uint64_t n_deadlocks;
+  uint64_t n_deadlocks_listed; // n_deadlocks when it is at most the cap, else 0
+  uint32_t* deadlocks;         // n_deadlocks_listed x words, sorted
+  uint64_t digest[2];          // digest of the reachable set
+  uint64_t dead_digest[2];     // digest of the deadlock set
+  uint64_t index_space;        // product of the locally reachable state counts
+  uint32_t* visited;           // n_states x words, sorted (only when requested)
+};
+
+void oracle_dense_result_free(oracle_dense_result* r) {
+  if (!r) return;
+  std::free(r->levels);
+  std::free(r->deadlocks);
+  std::free(r->visited);
+  r->levels = nullptr;
+  r->deadlocks = nullptr;
+  r->visited = nullptr;
+}
+
+// The same level-synchronous breadth-first search as oracle_explore (Sec. 3),
+// for state spaces too large for a hash set: the visited set, the current
+// level and the next level are dense bitmaps over the product of the
+// processes' locally reachable states (every reachable product state lies in
+// that product), indexed mixed-radix, and the states of a level are expanded
+// by n_threads threads.  A level holds exactly the states at distance k
+// whatever order the threads take, so every result is deterministic.
+// Successors follow the same semantics as successors() above: a transition
+// whose label a rule names at its process fires only through rules, all
+// participants stepping together; every other transition fires alone.
+//
+// Returns 0, -1 on an invalid network, -2 when the index space exceeds
+// max_index_space, -3 when the bitmaps cannot be allocated.
+int oracle_explore_dense(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                         const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                         const uint32_t* dst, uint32_t n_labels, uint32_t R,
+                         const int32_t* rules, uint32_t n_threads, uint64_t max_index_space,
+                         uint64_t dead_cap, int want_visited, oracle_dense_result* out) {
+  Net net;
+  Plan plan;
+  if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
+                          &net))
+    return -1;
+  if (!make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
+  if (n_threads == 0) n_threads = std::max(1u, std::thread::hardware_concurrency());
+
+  // Locally reachable states of each process: the closure of its initial state
+  // under all of its transitions.  digit d of process p stands for local state
+  // reach[p][d].
+  std::vector<std::vector<uint32_t>> reach(P);
+  std::vector<std::vector<int64_t>> digit_of(P);
+  for (uint32_t p = 0; p < P; ++p) {
+    std::vector<bool> seen(net.n_states[p], false);
+    std::vector<uint32_t> stack{net.initial[p]};
+    seen[net.initial[p]] = true;
+    while (!stack.empty()) {
+      uint32_t s = stack.back();
+      stack.pop_back();
+      for (const Trans& t : net.out[p][s])
+        if (!seen[t.dst]) {
+          seen[t.dst] = true;
+          stack.push_back(t.dst);
+        }
+    }
+    digit_of[p].assign(net.n_states[p], -1);
+    for (uint32_t s = 0; s < net.n_states[p]; ++s)
+      if (seen[s]) {
+        digit_of[p][s] = int64_t(reach[p].size());
+        reach[p].push_back(s);
+      }
+  }
+  std::vector<uint64_t> radix(P, 1);
+  uint64_t total = 1;
+  for (uint32_t p = 0; p < P; ++p) {
+    radix[p] = total;
+    if (total > max_index_space / reach[p].size()) return -2;
+    total *= reach[p].size();
+  }
+  // Per process and digit: the targets (as digits) of the transitions that
+  // fire alone; per rule and participant: the targets of its matching ones.
+  std::vector<std::vector<std::vector<uint32_t>>> alone(P);
+  for (uint32_t p = 0; p < P; ++p) {
+    alone[p].resize(reach[p].size());
+    for (size_t d = 0; d < reach[p].size(); ++d)
+      for (const Trans& t : net.out[p][reach[p][d]])
+        if (!net.governed[p][t.label]) alone[p][d].push_back(uint32_t(digit_of[p][t.dst]));
+  }
+  struct Part {
+    uint32_t p;
+    std::vector<std::vector<uint32_t>> to;  // digit -> target digits
+  };
+  std::vector<std::vector<Part>> rule_parts(R);
+  for (uint32_t r = 0; r < R; ++r)
+    for (uint32_t p = 0; p < P; ++p) {
+      const int32_t a = net.rules[size_t(r) * P + p];
+      if (a < 0) continue;
+      Part part{p, std::vector<std::vector<uint32_t>>(reach[p].size())};
+      for (size_t d = 0; d < reach[p].size(); ++d)
+        for (const Trans& t : net.out[p][reach[p][d]])
+          if (t.label == uint32_t(a)) part.to[d].push_back(uint32_t(digit_of[p][t.dst]));
+      rule_parts[r].push_back(std::move(part));
+    }
+
+  const uint64_t n_words = (total + 63) / 64;
+  auto alloc = [&](void) {
+    return static_cast<uint64_t*>(std::calloc(n_words, sizeof(uint64_t)));
+  };
+  std::unique_ptr<uint64_t, decltype(&std::free)> visited(alloc(), &std::free),
+      cur(alloc(), &std::free), nxt(alloc(), &std::free);
+  if (!visited || !cur || !nxt) return -3;
+  uint64_t* V = visited.get();
+  uint64_t* F = cur.get();
+  uint64_t* N = nxt.get();
+
+  uint64_t init = 0;
+  for (uint32_t p = 0; p < P; ++p) init += uint64_t(digit_of[p][net.initial[p]]) * radix[p];
+  V[init / 64] |= uint64_t(1) << (init % 64);
+  F[init / 64] |= uint64_t(1) << (init % 64);
+
+  auto digits_of = [&](uint64_t idx, uint32_t* d) {
+    for (uint32_t p = 0; p < P; ++p) {
+      d[p] = uint32_t(idx % reach[p].size());
+      idx /= reach[p].size();
+    }
+  };
+  auto packed = [&](const uint32_t* d) {
+    std::vector<uint32_t> local(P);
+    for (uint32_t p = 0; p < P; ++p) local[p] = reach[p][d[p]];
+    return pack(plan, local);
+  };
+
+  struct Acc {
+    uint64_t fresh = 0, trans = 0, dead = 0;
+    uint64_t dead_digest[2] = {0, 0};
+    std::vector<uint64_t> dead_idx;
+  };
+  std::vector<Acc> acc(n_threads);
+  std::vector<uint64_t> levels{1};
+  constexpr uint64_t kChunk = 1024;  // bitmap words per unit of work
+
+  auto expand_level = [&](uint32_t tid, std::atomic<uint64_t>* next_chunk) {
+    Acc& a = acc[tid];
+    std::vector<uint32_t> d(P);
+    std::vector<size_t> pick;
+    auto visit = [&](uint64_t s) {
+      ++a.trans;
+      uint64_t* wv = V + s / 64;
+      const uint64_t bit = uint64_t(1) << (s % 64);
+      if (__atomic_load_n(wv, __ATOMIC_RELAXED) & bit) return;
+      if (__atomic_fetch_or(wv, bit, __ATOMIC_RELAXED) & bit) return;
+      __atomic_fetch_or(N + s / 64, bit, __ATOMIC_RELAXED);
+      ++a.fresh;
+    };
+    while (true) {
+      const uint64_t c = next_chunk->fetch_add(1);
+      if (c * kChunk >= n_words) break;
+      const uint64_t end = std::min(n_words, (c + 1) * kChunk);
+      for (uint64_t wi = c * kChunk; wi < end; ++wi) {
+        uint64_t x = F[wi];
+        if (!x) continue;
+        F[wi] = 0;  // consumed: this bitmap is the next level's after the swap
+        while (x) {
+          const uint64_t idx = wi * 64 + uint64_t(__builtin_ctzll(x));
+          x &= x - 1;
+          digits_of(idx, d.data());
+          const uint64_t before = a.trans;
+          for (uint32_t p = 0; p < P; ++p)
+            for (uint32_t t : alone[p][d[p]])
+              visit(idx - uint64_t(d[p]) * radix[p] + uint64_t(t) * radix[p]);
+          for (uint32_t r = 0; r < R; ++r) {
+            const std::vector<Part>& parts = rule_parts[r];
+            bool blocked = false;
+            for (const Part& q : parts) blocked |= q.to[d[q.p]].empty();
+            if (blocked) continue;
+            pick.assign(parts.size(), 0);
+            while (true) {  // every choice of one matching transition per participant
+              uint64_t s = idx;
+              for (size_t i = 0; i < parts.size(); ++i) {
+                const Part& q = parts[i];
+                s = s - uint64_t(d[q.p]) * radix[q.p] +
+                    uint64_t(q.to[d[q.p]][pick[i]]) * radix[q.p];
+              }
+              visit(s);
+              size_t i = 0;
+              while (i < parts.size() && ++pick[i] == parts[i].to[d[parts[i].p]].size())
+                pick[i++] = 0;
+              if (i == parts.size()) break;
+            }
+          }
+          if (a.trans == before) {  // no product transition: a deadlock
+            ++a.dead;
+            digest_add(packed(d.data()), plan.words, a.dead_digest);
+            if (a.dead_idx.size() <= dead_cap) a.dead_idx.push_back(idx);
+          }
+        }
+      }
+    }
+  };
+
+  while (true) {
+    std::atomic<uint64_t> next_chunk{0};
+    for (Acc& a : acc) a.fresh = 0;
+    std::vector<std::thread> pool;
+    for (uint32_t t = 0; t < n_threads; ++t) pool.emplace_back(expand_level, t, &next_chunk);
+    for (std::thread& th : pool) th.join();
+    uint64_t fresh = 0;
+    for (const Acc& a : acc) fresh += a.fresh;
+    if (fresh == 0) break;
+    levels.push_back(fresh);
+    std::swap(F, N);
+  }
+
+  // Count, digest (and optionally list) the visited set.
+  struct Scan {
+    uint64_t n = 0;
+    uint64_t digest[2] = {0, 0};
+    std::vector<Vec> vis;
+  };
+  std::vector<Scan> scans(n_threads);
+  {
+    std::atomic<uint64_t> next_chunk{0};
+    auto scan = [&](uint32_t tid) {
+      Scan& sc = scans[tid];
+      std::vector<uint32_t> d(P);
+      while (true) {
+        const uint64_t c = next_chunk.fetch_add(1);
+        if (c * kChunk >= n_words) break;
+        const uint64_t end = std::min(n_words, (c + 1) * kChunk);
+        for (uint64_t wi = c * kChunk; wi < end; ++wi)
+          for (uint64_t x = V[wi]; x; x &= x - 1) {
+            digits_of(wi * 64 + uint64_t(__builtin_ctzll(x)), d.data());
+            const Vec v = packed(d.data());
+            ++sc.n;
+            digest_add(v, plan.words, sc.digest);
+            if (want_visited) sc.vis.push_back(v);
+          }
+      }
+    };
+    std::vector<std::thread> pool;
+    for (uint32_t t = 0; t < n_threads; ++t) pool.emplace_back(scan, t);
+    for (std::thread& th : pool) th.join();
+  }
+
+  uint64_t n_reach = 0, transitions = 0, n_dead = 0;
+  uint64_t digest[2] = {0, 0}, dead_digest[2] = {0, 0};
+  std::vector<Vec> dead, vis;
+  for (const Scan& sc : scans) {
+    n_reach += sc.n;
+    for (int k = 0; k < 2; ++k) digest[k] = (digest[k] + sc.digest[k]) % kDigestP;
+    if (want_visited) vis.insert(vis.end(), sc.vis.begin(), sc.vis.end());
+  }
+  for (const Acc& a : acc) {
+    transitions += a.trans;
+    n_dead += a.dead;
+    for (int k = 0; k < 2; ++k) dead_digest[k] = (dead_digest[k] + a.dead_digest[k]) % kDigestP;
+  }
+  if (n_dead <= dead_cap) {
+    std::vector<uint32_t> d(P);
+    for (const Acc& a : acc)
+      for (uint64_t idx : a.dead_idx) {
+        digits_of(idx, d.data());
+        dead.push_back(packed(d.data()));
+      }
+  }
+  uint64_t level_sum = 0;
+  for (uint64_t l : levels) level_sum += l;
+  if (level_sum != n_reach) return -4;  // cannot happen: every visited bit is counted once
+
+  oracle_result base{};
+  fill_result(plan, levels, n_reach, transitions, dead, want_visited ? &vis : nullptr, &base);
+  out->words = base.words;
+  out->n_levels = base.n_levels;
+  out->n_states = base.n_states;
+  out->n_transitions = base.n_transitions;
+  out->levels = base.levels;
+  out->n_deadlocks = n_dead;
+  out->n_deadlocks_listed = base.n_deadlocks;
+  out->deadlocks = base.deadlocks;
+  out->visited = base.visited;
+  for (int k = 0; k < 2; ++k) {
+    out->digest[k] = digest[k];
+    out->dead_digest[k] = dead_digest[k];
+  }
+  out->index_space = total;
   return 0;
 }
 

@@ -28,6 +28,7 @@ EMPTY_WORD = 0xFFFFFFFF
 EXPORTED = [
     "gx_table_create", "gx_table_destroy", "gx_table_clear", "gx_find_or_put",
     "gx_table_get_info", "gx_table_stats", "gx_table_dump", "gx_table_read_raw",
+    "gx_table_copy_raw",
     "gx_hash_bucket", "gx_network_words", "gx_network_pack", "gx_explore",
     "gx_explore_result_free", "gx_status_str", "gx_gather_probe",
     "gx_batch_create", "gx_batch_run", "gx_batch_results", "gx_batch_instance_config",
@@ -145,6 +146,8 @@ def lib() -> ctypes.CDLL:
         L.gx_table_dump.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
         L.gx_table_read_raw.restype = st
         L.gx_table_read_raw.argtypes = [vp, vp, u64, u64]
+        L.gx_table_copy_raw.restype = st
+        L.gx_table_copy_raw.argtypes = [vp, vp, u64, u64, vp]
         L.gx_hash_bucket.restype = st
         L.gx_hash_bucket.argtypes = [vp, u32, u64, u32, u64, ctypes.POINTER(u64)]
         L.gx_network_words.restype = st
@@ -321,6 +324,13 @@ class Table:
         _check(lib().gx_table_read_raw(self.handle, out.ctypes.data, first_word, n_words),
                "gx_table_read_raw")
         return out
+
+    def copy_raw(self, out, first_word: int = 0, stream=None) -> None:
+        """Copy raw storage words [first_word, first_word + out.numel()) into the
+        device tensor ``out`` (int32 or uint32), stream-ordered."""
+        _check(lib().gx_table_copy_raw(self.handle, _dev_ptr(out, "out"), first_word,
+                                       out.numel(), _stream_handle(stream)),
+               "gx_table_copy_raw")
 
 
 def hash_bucket(key, words_per_state: int, hash_seed: int, j: int, n_buckets: int) -> int:

@@ -276,6 +276,18 @@ gx_status gx_table_read_raw(gx_table* t, uint32_t* host, uint64_t first, uint64_
   return GX_OK;
 }
 
+gx_status gx_table_copy_raw(gx_table* t, uint32_t* dev_words, uint64_t first, uint64_t n_words,
+                            void* stream) {
+  if (!t || (!dev_words && n_words)) return GX_EINVAL;
+  const uint64_t total = t->n_buckets * t->B;
+  if (first > total || n_words > total - first) return GX_EINVAL;
+  if (n_words == 0) return GX_OK;
+  if (hipMemcpyAsync(dev_words, t->words + first, n_words * sizeof(uint32_t),
+                     hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return GX_EDEVICE;
+  return GX_OK;
+}
+
 gx_status gx_table_dump(gx_table* t, uint32_t* host_keys, uint64_t cap, uint64_t* n_out) {
   if (!t || !n_out) return GX_EINVAL;
   const uint64_t total = t->n_buckets * t->B;

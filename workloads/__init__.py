@@ -255,6 +255,12 @@ def large_random_network(live: int = 8) -> Network:
 # factor 0.28 at its 3.3e9 states.
 LARGE_TABLE_SLOTS = 12_000_000_000
 
+# Table configuration of the large workload's exploration, the one the
+# benchmark times and the full-size parity test checks: buckets of 16 words
+# (four 16-byte slots, one 64-byte granule), 4-lane subgroups, one key in
+# flight per subgroup, 16 hash functions.
+LARGE_EXPLORE = {"bucket_words": 16, "subgroup": 4, "keys_per_subgroup": 1, "max_hashes": 16}
+
 
 # ------------------------------------------------------------- key streams
 MASK62 = (1 << 62) - 1
@@ -442,3 +448,41 @@ def batch_networks(n: int, seed: int, log10_lo: float = 3.0, log10_hi: float = 7
                                name=f"batch_{seed}_{i}"))
         caps.append(int(math.prod(m)))
     return nets, caps
+
+
+# --------------------------------------------------- served exploration requests
+def served_networks(n: int, seed: int, log10_lo: float = 4.0, log10_hi: float = 8.0,
+                    out_degree: int = 3):
+    """n random networks for the served workload, sizes and vector widths
+    decoupled.
+
+    Request i: a target T ~ log-uniform [10^lo, 10^hi] and a width w ~ U{1..4}
+    words; P processes of 64 declared states (6-bit fields, five per word),
+    P ~ U{5(w-1)+1 .. 5w} raised until 64^P >= 4T; live counts m_p
+    (1 <= m_p <= 64) raised round-robin while prod m_p <= 4T.  Every reachable
+    local state is live, so prod m_p bounds the reachable set.  The declared
+    bound of a request is 2T.  Returns (networks, targets)."""
+    import math
+
+    rng = SplitMix64(seed)
+    nets, targets = [], []
+    for i in range(n):
+        u = rng.next() / 2.0**64
+        target = 10 ** (log10_lo + (log10_hi - log10_lo) * u)
+        w = 1 + rng.below(4)
+        P = 5 * (w - 1) + 1 + rng.below(5)
+        while 64 ** P < 4 * target and P < 5 * w:
+            P += 1
+        want = 4.0 * target
+        m = [1] * P
+        grew = True
+        while grew:
+            grew = False
+            for p in range(P):
+                if m[p] < 64 and math.prod(m) / m[p] * (m[p] + 1) <= want:
+                    m[p] += 1
+                    grew = True
+        nets.append(random_lts(seed * 1000003 + i, P, 64, m, out_degree, 32, 0.25, 0.05,
+                               name=f"served_{seed}_{i}"))
+        targets.append(int(target))
+    return nets, targets
