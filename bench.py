@@ -66,12 +66,10 @@ def parse():
     ap.add_argument("--batch-subgroup", type=int, default=0, help="0: autotuned per instance")
     ap.add_argument("--batch-kps", type=int, default=0, help="0: autotuned per instance")
     ap.add_argument("--serve", action="store_true",
-                    help="served exploration: Poisson request streams at several rates")
-    ap.add_argument("--serve-n", type=int, default=120, help="requests per rate")
+                    help="served exploration: Poisson request streams at 0.1-1.2x saturation")
+    ap.add_argument("--serve-n", type=int, default=1000, help="requests per rate")
     ap.add_argument("--tiny", action="store_true",
                     help="only the tiny configuration")
-    ap.add_argument("--serve-sweep", action="store_true",
-                    help="served exploration at 0.1-1.2x the saturation rate, 1000 requests each")
     ap.add_argument("--dup-sweep", action="store_true",
                     help="isolated insertion of 2^27 one-word keys at duplication 1..64")
     ap.add_argument("--token-ring", action="store_true",
@@ -467,110 +465,124 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
         "configs": {f"B{B}-G{G}-U{U}": c for (B, G, U), c in Counter(cfgs).items()}}}
 
 
-def run_serve(gx, torch, W, n_req, seed=5, rates=(0.25, 1.0, 4.0), relative="alone"):
-    """Served exploration: Poisson arrivals of requests with reachable sizes
-    spread log-uniformly over 1e4-1.4e8 (token rings of 7-15 nodes, sizes
-    known in closed form) plus three- and four-word random networks; the
-    declared bound is 1.25x the size.  Rates are multiples of the rate at
-    which the server completes them back to back (relative="alone") or of
-    its saturation rate, all requests submitted at once ("saturation"); both
-    are measured first."""
+def load_served_pool():
+    """Exact results of the served request pool, computed by the CPU oracle
+    and stored by tests/golden/make_served_pool.py: {index: dict}."""
+    rows = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "served_pool.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x) for x in line.split()]
+        rows[v[0]] = {"words": v[1], "states": v[2], "transitions": v[3], "deadlocks": v[4],
+                      "levels": v[7:]}
+    return rows
+
+
+def _wrong(st, r, want, gx) -> int:
+    """1 when a served result differs from the oracle's (state, transition and
+    deadlock counts and every level count), else 0."""
+    return int(st != gx.GX_OK or r.n_states != want["states"]
+               or r.n_transitions != want["transitions"]
+               or len(r.deadlocks) != want["deadlocks"]
+               or r.levels.tolist() != want["levels"])
+
+
+def run_serve(gx, torch, W, n_req=1000, seed=5, rates=(0.1, 0.25, 0.5, 0.75, 1.0, 1.2),
+              budget_gib=200):
+    """Served exploration: requests drawn (seeded) from a pool of 256 random
+    networks with reachable sizes spread log-uniformly over 1e4-1e8 and 1- to
+    4-word vectors (W.served_networks(256, 5)), each declaring the product of
+    its live-state counts as its bound.  Measured: the saturation rate (all
+    n_req requests submitted at once), then Poisson streams of n_req requests
+    (seeded exponential gaps) at each multiple of it in ``rates``, with p50/p99
+    latency from submission to result; every result is checked against the
+    oracle's (tests/golden/served_pool.txt).  Reference: one gx_explore call
+    per request, back to back, on a resident table in the server's kernel
+    configuration (each pool network timed once on its warm table; the
+    reference time is the sum over the requests)."""
     import random
 
+    nets, _, bounds = W.served_networks(256, 5)
+    want = load_served_pool()
     rng = random.Random(seed)
-    pool = []
-    for n_nodes in range(7, 16):
-        pool.append((W.token_ring(n_nodes), 2 * n_nodes * 3 ** (n_nodes - 1)))
-    extra = [W.random_lts(303, 12, 64, 3, 3, 32, 0.25, 0.1),
-             W.random_lts(404, 16, 64, 2, 3, 32, 0.25, 0.0)]
-    out = []
-    with gx.Server(200 << 30, max_hashes=16) as srv:
-        # sizes of the random networks
-        for nt in extra:
-            rid = srv.submit(nt, 1 << 20)
-            st, r, _ = srv.poll(rid)
-            pool.append((nt, r.n_states))
-        reqs = [pool[rng.randrange(len(pool))] for _ in range(n_req)]
-        total_states = sum(sz for _, sz in reqs)
-        # one exploration call per request (gx_explore into a resident table of
-        # the request's network, cleared first): the one-launch-per-instance
-        # reference
-        tables = {}
-        for nt, sz in pool:
-            w = gx.network_words(nt)
-            tb, tg, _ = gx.autotune(w, 0.5)  # the server's kernel configuration
-            tables[id(nt)] = gx.Table(w, tb, max(64, int(sz * 2.5)), subgroup=tg,
-                                      keys_per_subgroup=1, max_hashes=16)
-            gx.explore(nt, tables[id(nt)])  # sizes its resident buffers
+    reqs = [rng.randrange(len(nets)) for _ in range(n_req)]
+    total_states = sum(want[i]["states"] for i in reqs)
+    # one gx_explore call per pool network on a warm, resident table
+    t_net = {}
+    cfg_of = {}
+    for i in sorted(set(reqs)):
+        nt = nets[i]
+        w = gx.network_words(nt)
+        tb, tg, _ = gx.autotune(w, 0.5)  # the server's kernel configuration
+        cfg_of[i] = (tb, 4 if w == 3 else w)
+        t = gx.Table(w, tb, max(64, 2 * want[i]["states"]), subgroup=tg, keys_per_subgroup=1,
+                     max_hashes=16)
+        gx.explore(nt, t)  # sizes its resident buffers
+        t.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for nt, sz in reqs:
-            t = tables[id(nt)]
-            t.clear()
-            gx.explore(nt, t)
-        torch.cuda.synchronize()
-        single = time.perf_counter() - t0
-        for t in tables.values():
-            t.close()
-        out.append({"served": "one gx_explore call per request, back to back",
-                    "requests": n_req, "seconds": round(single, 3),
-                    "states_per_s": round(total_states / single)})
-        # back to back, one at a time: the service rate
-        t0 = time.perf_counter()
-        for nt, sz in reqs:
-            srv.poll(srv.submit(nt, int(sz * 1.25)))
-        alone = time.perf_counter() - t0
-        rate_alone = n_req / alone
-        out.append({"served": "one at a time", "requests": n_req, "seconds": round(alone, 3),
-                    "states_per_s": round(total_states / alone)})
+        r = gx.explore(nt, t)
+        t_net[i] = time.perf_counter() - t0
+        if _wrong(gx.GX_OK, r, want[i], gx):
+            raise SystemExit(f"served pool network {i}: gx_explore differs from the oracle")
+        t.close()
+    torch.cuda.empty_cache()
+    single = sum(t_net[i] for i in reqs)
+    algo = sum(want[i]["states"] * explore_bytes_per_state(
+        want[i]["transitions"] / max(1, want[i]["states"]), *cfg_of[i]) for i in reqs)
+    out = {"workload": (f"{n_req} requests drawn from 256 random networks, reachable sizes "
+                        f"log-uniform 1e4-1e8 ({min(want[i]['states'] for i in reqs)}-"
+                        f"{max(want[i]['states'] for i in reqs)} drawn), 1-4-word vectors, "
+                        "declared bound = product of live-state counts; Poisson arrivals"),
+           "requests": n_req, "states_per_rate": total_states,
+           "one_call_per_request_states_per_s": round(total_states / single)}
+    with gx.Server(budget_gib << 30, max_hashes=16) as srv:
         # all at once: the saturation rate
         t0 = time.perf_counter()
-        ids = [srv.submit(nt, int(sz * 1.25)) for nt, sz in reqs]
-        burst_bad = 0
-        for rid, (nt, sz) in zip(ids, reqs):
+        ids = [srv.submit(nets[i], bounds[i]) for i in reqs]
+        bad = 0
+        for rid, i in zip(ids, reqs):
             st, r, _ = srv.poll(rid)
-            burst_bad += int(st != gx.GX_OK or r.n_states != sz)
+            bad += _wrong(st, r, want[i], gx)
         burst = time.perf_counter() - t0
         rate_sat = n_req / burst
-        out.append({"served": "all submitted at once (saturation)", "requests": n_req,
-                    "seconds": round(burst, 3), "states_per_s": round(total_states / burst),
-                    "requests_per_s": round(rate_sat, 2), "wrong_results": burst_bad,
-                    "vs_one_call_per_request": round(single / burst, 2)})
-        print(json.dumps(out[-1]), file=sys.stderr, flush=True)
-        base = rate_sat if relative == "saturation" else rate_alone
-        label = "saturation" if relative == "saturation" else "one-at-a-time"
+        out["saturation"] = {"seconds": round(burst, 3), "requests_per_s": round(rate_sat, 2),
+                             "states_per_s": round(total_states / burst),
+                             "wrong_results": bad,
+                             "vs_one_call_per_request": round(single / burst, 2),
+                             "roofline": roofline_of(total_states, algo, burst)}
+        print(json.dumps({"served": "saturation", **out["saturation"]}), file=sys.stderr,
+              flush=True)
+        out["rates"] = []
         for mult in rates:
-            lam = mult * base
-            t_arr = 0.0
-            times = []
+            lam = mult * rate_sat
+            t_arr, times = 0.0, []
             for _ in range(n_req):
                 t_arr += rng.expovariate(lam)
                 times.append(t_arr)
             ids = []
             start = time.perf_counter()
-            for (nt, sz), ta in zip(reqs, times):
+            for i, ta in zip(reqs, times):
                 now = time.perf_counter() - start
                 if ta > now:
                     time.sleep(ta - now)
-                ids.append(srv.submit(nt, int(sz * 1.25)))
-            lat = []
-            bad = 0
-            for rid, (nt, sz) in zip(ids, reqs):
+                ids.append(srv.submit(nets[i], bounds[i]))
+            lat, bad = [], 0
+            for rid, i in zip(ids, reqs):
                 st, r, l = srv.poll(rid)
                 lat.append(l)
-                bad += int(st != gx.GX_OK or r.n_states != sz)
+                bad += _wrong(st, r, want[i], gx)
             wall = time.perf_counter() - start
             lat.sort()
             stt = srv.stats()
-            out.append({"served": f"Poisson, rate {mult}x the {label} rate",
-                        "requests": n_req, "rate_per_s": round(lam, 2),
-                        "seconds": round(wall, 3), "states_per_s": round(total_states / wall),
-                        "p50_latency_s": round(lat[len(lat) // 2], 4),
-                        "p99_latency_s": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
-                        "wrong_results": bad, "active_peak": stt["active_peak"],
-                        "retried": stt["retried"],
-                        "vs_one_call_per_request": round(single / wall, 2)})
-            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+            row = {"rate_vs_saturation": mult, "rate_per_s": round(lam, 2),
+                   "seconds": round(wall, 3), "states_per_s": round(total_states / wall),
+                   "p50_latency_s": round(lat[len(lat) // 2], 4),
+                   "p99_latency_s": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
+                   "wrong_results": bad, "retried": stt["retried"],
+                   "vs_one_call_per_request": round(single / wall, 2)}
+            out["rates"].append(row)
+            print(json.dumps({"served": "poisson", **row}), file=sys.stderr, flush=True)
     return out
 
 
@@ -624,18 +636,11 @@ def main():
                                    G=args.batch_subgroup, U=args.batch_kps)), flush=True)
         return
     if args.serve:
-        for row in run_serve(gx, torch, W, args.serve_n):
-            print(json.dumps(row), flush=True)
+        print(json.dumps(run_serve(gx, torch, W, args.serve_n)), flush=True)
         return
     if args.tiny:
         print(json.dumps(run_tiny(gx, torch, W)), flush=True)
         return
-    if args.serve_sweep:
-        for row in run_serve(gx, torch, W, max(args.serve_n, 1000),
-                             rates=(0.1, 0.25, 0.5, 0.75, 1.0, 1.2), relative="saturation"):
-            print(json.dumps(row), flush=True)
-        return
-
     if args.explore:
         for spec in args.net or ["1:12:64:5:3:0.2"]:
             seed, P, ns, live, deg, sink = spec.split(":")
@@ -781,17 +786,7 @@ def main():
         out.update(run_batch(gx, torch, W, args.batch_n, B=args.batch_bucket,
                              G=args.batch_subgroup, U=args.batch_kps))
     if not args.no_serve:
-        rows = run_serve(gx, torch, W, args.serve_n, rates=(1.0, 4.0))
-        out["served"] = {
-            "workload": ("Poisson request streams (token rings of 7-15 nodes and two random "
-                         "networks, 1e4-1.4e8 states, 1-4 words), bound declared 1.25x"),
-            "one_call_per_request_states_per_s": rows[0]["states_per_s"],
-            "saturation": {k: rows[2][k] for k in ("requests_per_s", "states_per_s",
-                                                   "wrong_results",
-                                                   "vs_one_call_per_request")},
-            "rates": [{k: r[k] for k in ("rate_per_s", "states_per_s", "p50_latency_s",
-                                         "p99_latency_s", "wrong_results",
-                                         "vs_one_call_per_request")} for r in rows[3:]]}
+        out["served"] = run_serve(gx, torch, W, args.serve_n)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
         if not args.no_explore:

@@ -221,6 +221,48 @@ gx_status gx_network_words(const gx_network* net, uint32_t* words_per_state);
 gx_status gx_network_pack(const gx_network* net, const uint32_t* local, uint64_t n,
                           uint32_t* out);
 
+/*
+ * Automaton of a negated safety property (Sec. 3: such an automaton can be
+ * added to the network, and reaching one of its bad states during the
+ * exploration shows that the property is violated).  It observes actions of
+ * the network, numbered as follows: action r < n_rules is synchronisation
+ * rule r; action n_rules + l is label l fired alone by any process.
+ */
+typedef struct {
+  uint32_t n_states, initial, n_trans;
+  const uint32_t* src;     /* host, n_trans                                  */
+  const uint32_t* action;  /* host, n_trans: the action observed             */
+  const uint32_t* dst;     /* host, n_trans                                  */
+  const uint8_t* bad;      /* host, n_states: nonzero = bad state            */
+} gx_monitor;
+
+/* A network with a monitor as its last process (library-owned arrays). */
+typedef struct {
+  gx_network net;              /* pass to gx_network_words and gx_explore    */
+  uint32_t monitor_proc;       /* the automaton's process index (n_procs - 1) */
+  const uint8_t* monitor_bad;  /* its bad-state flags, for gx_explore_opts    */
+  void* owner;                 /* library-internal                            */
+} gx_monitored_network;
+
+/*
+ * Add a safety monitor to a network (Sec. 3), host only.  The automaton
+ * becomes one more process: a rule it observes gains it as a participant,
+ * and a label it observes that process p fires alone becomes a rule of p and
+ * the automaton (one rule per such process), each observed action with a
+ * label of its own; unobserved actions fire as before.  Where the automaton
+ * leaves an observed action unspecified in some state it stays in that state
+ * (it never blocks the network); observed actions the network never
+ * performs are dropped.  Explore the result with opts.monitor_proc =
+ * out->monitor_proc and opts.monitor_bad = out->monitor_bad; free it with
+ * gx_monitored_network_free.  Errors: GX_EINVAL (invalid network or
+ * automaton, an action out of range), GX_ENOMEM.
+ */
+gx_status gx_network_add_monitor(const gx_network* net, const gx_monitor* mon,
+                                 gx_monitored_network* out);
+
+/* Release what gx_network_add_monitor allocated.  NULL is accepted. */
+void gx_monitored_network_free(gx_monitored_network* m);
+
 typedef struct {
   uint64_t frontier_capacity; /* largest BFS level (states) the call may buffer;
                                  0 -> limited by device memory only           */
@@ -259,6 +301,10 @@ typedef struct {
   uint32_t violation_level; /* first level holding a violation; 0xFFFFFFFF
                                when none                                      */
   uint32_t reserved;
+  uint32_t* states;       /* the reachable states (the table's contents),
+                             n_states x w words, sorted (library-owned); only
+                             when asked for (keep_states of a batch or a
+                             server), else NULL                               */
 } gx_explore_result;
 
 /*
@@ -333,10 +379,20 @@ typedef struct {
   uint32_t use_graph;         /* nonzero: gx_batch_create captures a whole run
                                  (clears, resets and every launch) in a hipGraph
                                  and gx_batch_run replays it                   */
-  uint32_t max_levels;        /* BFS levels per instance; 0 -> 4096            */
+  uint32_t max_levels;        /* BFS levels per instance; 0 -> 4096.  An
+                                 instance deeper than this gets GX_ENOMEM.  The
+                                 device work queue holds instances x
+                                 max_levels entries of 32 bytes, so every
+                                 level of every instance fits; instances x
+                                 max_levels must stay below 2^31 (else
+                                 GX_EINVAL)                                   */
   uint64_t deadlock_capacity; /* deadlock records per class; 0 -> min(sum of
                                  capacities, 2^26)                             */
   void* hip_stream;           /* stream used by gx_explore_batch               */
+  uint32_t keep_states;       /* nonzero: gx_batch_results also returns every
+                                 instance's reachable states (its table
+                                 partition's contents) in outs[i].states      */
+  uint32_t reserved;
 } gx_batch_opts;
 
 /* Compile every network (argument errors before device work), choose each
@@ -409,7 +465,10 @@ typedef struct {
   uint32_t subgroup;          /* 0 -> autotuned, else 4|8|16 (4 with buckets
                                  of at most 32 words)                         */
   uint32_t keys_per_subgroup; /* 0 -> 1, else 1|2                             */
-  uint32_t reserved;
+  uint32_t keep_states;       /* nonzero: a completed request's result also
+                                 holds its reachable states (its table's
+                                 contents, read before the table is released)
+                                 in result.states                              */
 } gx_server_opts;
 
 typedef struct {

@@ -122,6 +122,9 @@ def _load():
                                                      ctypes.POINTER(u64)]
         lib.oracle_free.argtypes = [vp]
         lib.oracle_digest.argtypes = [u32, vp, u64, vp]
+        lib.oracle_explore_automaton.restype = i32
+        lib.oracle_explore_automaton.argtypes = net_args + [u32, u32, u32, vp, vp, vp, vp, u32,
+                                                            i32, i32, ctypes.POINTER(_Result)]
         lib.oracle_explore_dense.restype = i32
         lib.oracle_explore_dense.argtypes = net_args + [u32, u64, u64, i32,
                                                         ctypes.POINTER(_DenseResult)]
@@ -249,6 +252,31 @@ def explore(net, max_states: int = 0, want_visited: bool = False,
         raise ValueError("invalid network")
     if rc == -2:
         raise OverflowError("more than max_states reachable states")
+    return _collect(res, want_visited)
+
+
+def explore_automaton(net, automaton, bad, want_visited: bool = False, max_levels: int = 0,
+                      stop_on_violation: bool = False) -> OracleResult:
+    """BFS of the network watched by the automaton of a negated safety
+    property (Sec. 3), from the meaning of observation rather than by
+    composing a network: automaton = (n_states, initial, [(src, action,
+    dst)]), actions r < n_rules for rule r and n_rules + l for label l fired
+    alone; ``bad`` lists its bad states.  The state packs the automaton as one
+    more process after the network's."""
+    args, keep = _flatten(net)
+    n, init, trans = automaton
+    t = np.asarray(trans, dtype=np.uint32).reshape(-1, 3)
+    src, act, dst = (np.ascontiguousarray(t[:, i]) for i in range(3))
+    flags = np.zeros(max(1, int(n)), dtype=np.uint8)
+    flags[list(bad)] = 1
+    res = _Result()
+    rc = _load().oracle_explore_automaton(*args, int(n), int(init), t.shape[0], _ptr(src),
+                                          _ptr(act), _ptr(dst), _ptr(flags), max_levels,
+                                          int(want_visited), int(stop_on_violation),
+                                          ctypes.byref(res))
+    del keep
+    if rc == -1:
+        raise ValueError("invalid network or automaton")
     return _collect(res, want_visited)
 
 

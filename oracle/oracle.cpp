@@ -188,9 +188,13 @@ bool load_net(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
 }
 
 // All product successors of the unpacked state `local`, with multiplicity.
+// With `actions`, also the action each one performs: a transition that fires
+// alone performs action R + its label, rule r performs action r.
 void successors(const Net& net, const std::vector<uint32_t>& local,
-                std::vector<std::vector<uint32_t>>* succ) {
+                std::vector<std::vector<uint32_t>>* succ,
+                std::vector<uint32_t>* actions = nullptr) {
   succ->clear();
+  if (actions) actions->clear();
   // transitions that fire alone
   for (uint32_t p = 0; p < net.P; ++p) {
     for (const Trans& t : net.out[p][local[p]]) {
@@ -198,6 +202,7 @@ void successors(const Net& net, const std::vector<uint32_t>& local,
       std::vector<uint32_t> s = local;
       s[p] = t.dst;
       succ->push_back(std::move(s));
+      if (actions) actions->push_back(net.R + t.label);
     }
   }
   // synchronisation rules: every participant takes one matching transition
@@ -210,6 +215,7 @@ void successors(const Net& net, const std::vector<uint32_t>& local,
     std::function<void(size_t)> choose = [&](size_t i) {
       if (i == parts.size()) {
         succ->push_back(cur);
+        if (actions) actions->push_back(r);
         return;
       }
       uint32_t q = parts[i];
@@ -375,11 +381,14 @@ static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
   }
 }
 
-// Plain breadth-first search over std::unordered_set.
-// Returns 0 on success, -1 on an invalid network, -2 when more than
-// max_states states are reachable (max_states == 0: no limit).  With
-// max_levels > 0 the search stops once levels 0 .. max_levels-1 are known
-// (a BFS prefix: level counts of those levels, the states at distance below
+using SuccFn =
+    std::function<void(const std::vector<uint32_t>&, std::vector<std::vector<uint32_t>>*)>;
+
+// Plain breadth-first search over std::unordered_set from the unpacked state
+// `init`, with the product successors given by succ_fn.  Returns 0, or -2 when
+// more than max_states states are reachable (max_states == 0: no limit).  With
+// max_levels > 0 the search stops once levels 0 .. max_levels-1 are known (a
+// BFS prefix: level counts of those levels, the states at distance below
 // max_levels, and transitions and deadlocks of the levels expanded so far).
 //
 // Safety monitor (Sec. 3: the negation of a safety property is an automaton
@@ -389,20 +398,9 @@ static void fill_result(const Plan& plan, const std::vector<uint64_t>& levels,
 // it is complete; the violating states and the first level that holds one
 // are returned.  With stop_on_violation the search ends there: that level is
 // counted but not expanded.
-int oracle_explore_monitored(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
-                             const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
-                             const uint32_t* dst, uint32_t n_labels, uint32_t R,
-                             const int32_t* rules, uint64_t max_states, uint32_t max_levels,
-                             int want_visited, int32_t monitor_proc, const uint8_t* monitor_bad,
-                             int stop_on_violation, oracle_result* out) {
-  Net net;
-  Plan plan;
-  if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
-                          &net))
-    return -1;
-  if (!make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
-  if (monitor_proc >= 0 && (uint32_t(monitor_proc) >= P || !monitor_bad)) return -1;
-
+static int bfs(const Plan& plan, const std::vector<uint32_t>& init_local, const SuccFn& succ_fn,
+        uint64_t max_states, uint32_t max_levels, int want_visited, int32_t monitor_proc,
+        const uint8_t* monitor_bad, int stop_on_violation, oracle_result* out) {
   VecSet visited;
   std::vector<Vec> frontier, next, dead, viol;
   std::vector<uint64_t> levels;
@@ -422,7 +420,7 @@ int oracle_explore_monitored(uint32_t P, const uint32_t* n_states, const uint32_
     }
   };
 
-  Vec init = pack(plan, net.initial);
+  Vec init = pack(plan, init_local);
   visited.insert(init);
   frontier.push_back(init);
   levels.push_back(1);
@@ -432,7 +430,7 @@ int oracle_explore_monitored(uint32_t P, const uint32_t* n_states, const uint32_
     if (max_levels && levels.size() >= max_levels) break;
     next.clear();
     for (const Vec& s : frontier) {
-      successors(net, unpack(plan, s), &succ);
+      succ_fn(unpack(plan, s), &succ);
       transitions += succ.size();
       if (succ.empty()) dead.push_back(s);
       for (const auto& t : succ) {
@@ -453,6 +451,94 @@ int oracle_explore_monitored(uint32_t P, const uint32_t* n_states, const uint32_
               out);
   set_violations(plan, viol, viol_level, out);
   return 0;
+}
+
+// Plain breadth-first search of the network's synchronous product (Sec. 3).
+// Returns 0 on success, -1 on an invalid network, -2 when more than
+// max_states states are reachable; max_levels and the monitor as for bfs().
+int oracle_explore_monitored(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                             const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                             const uint32_t* dst, uint32_t n_labels, uint32_t R,
+                             const int32_t* rules, uint64_t max_states, uint32_t max_levels,
+                             int want_visited, int32_t monitor_proc, const uint8_t* monitor_bad,
+                             int stop_on_violation, oracle_result* out) {
+  Net net;
+  Plan plan;
+  if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
+                          &net))
+    return -1;
+  if (!make_plan(P, n_states, &plan) || plan.words > kMaxWords) return -1;
+  if (monitor_proc >= 0 && (uint32_t(monitor_proc) >= P || !monitor_bad)) return -1;
+  SuccFn fn = [&](const std::vector<uint32_t>& local, std::vector<std::vector<uint32_t>>* succ) {
+    successors(net, local, succ);
+  };
+  return bfs(plan, net.initial, fn, max_states, max_levels, want_visited, monitor_proc,
+             monitor_bad, stop_on_violation, out);
+}
+
+// Exploration of a network watched by the automaton of a negated safety
+// property (Sec. 3), straight from the meaning of "the automaton observes the
+// network's actions", without composing a new network: the state is the
+// network's state plus the automaton's state (packed as one more process
+// after the network's); each product transition of the network (action r for
+// rule r, action R + l for label l fired alone) moves the automaton along each
+// of its transitions on that action when it observes the action (any of its
+// transitions carries it), stays put when it observes the action but has no
+// transition on it in its current state, and stays put for unobserved
+// actions.  A state whose automaton state is bad is a violation; max_levels,
+// stop_on_violation and the result as for bfs().
+int oracle_explore_automaton(uint32_t P, const uint32_t* n_states, const uint32_t* initial,
+                             const uint32_t* n_trans, const uint32_t* src, const uint32_t* label,
+                             const uint32_t* dst, uint32_t n_labels, uint32_t R,
+                             const int32_t* rules, uint32_t mon_states, uint32_t mon_initial,
+                             uint32_t mon_n_trans, const uint32_t* mon_src,
+                             const uint32_t* mon_action, const uint32_t* mon_dst,
+                             const uint8_t* mon_bad, uint32_t max_levels, int want_visited,
+                             int stop_on_violation, oracle_result* out) {
+  Net net;
+  if (P == 0 || !load_net(P, n_states, initial, n_trans, src, label, dst, n_labels, R, rules,
+                          &net))
+    return -1;
+  if (mon_states == 0 || mon_initial >= mon_states || !mon_bad) return -1;
+  const uint32_t n_actions = R + n_labels;
+  std::vector<std::vector<std::vector<uint32_t>>> moves(
+      mon_states, std::vector<std::vector<uint32_t>>(n_actions));
+  std::vector<bool> observed(n_actions, false);
+  for (uint32_t t = 0; t < mon_n_trans; ++t) {
+    if (mon_src[t] >= mon_states || mon_dst[t] >= mon_states || mon_action[t] >= n_actions)
+      return -1;
+    moves[mon_src[t]][mon_action[t]].push_back(mon_dst[t]);
+    observed[mon_action[t]] = true;
+  }
+  std::vector<uint32_t> sizes(n_states, n_states + P);
+  sizes.push_back(mon_states);
+  Plan plan;
+  if (!make_plan(P + 1, sizes.data(), &plan) || plan.words > kMaxWords) return -1;
+  std::vector<uint32_t> init = net.initial;
+  init.push_back(mon_initial);
+  std::vector<std::vector<uint32_t>> net_succ;
+  std::vector<uint32_t> acts;
+  SuccFn fn = [&](const std::vector<uint32_t>& local, std::vector<std::vector<uint32_t>>* succ) {
+    succ->clear();
+    const std::vector<uint32_t> net_local(local.begin(), local.begin() + P);
+    const uint32_t m = local[P];
+    successors(net, net_local, &net_succ, &acts);
+    for (size_t i = 0; i < net_succ.size(); ++i) {
+      std::vector<uint32_t> t = net_succ[i];
+      t.push_back(m);
+      const std::vector<uint32_t>& to = moves[m][acts[i]];
+      if (!observed[acts[i]] || to.empty()) {
+        succ->push_back(t);
+        continue;
+      }
+      for (uint32_t m2 : to) {
+        t[P] = m2;
+        succ->push_back(t);
+      }
+    }
+  };
+  return bfs(plan, init, fn, 0, max_levels, want_visited, int32_t(P), mon_bad,
+             stop_on_violation, out);
 }
 
 int oracle_explore(uint32_t P, const uint32_t* n_states, const uint32_t* initial,

@@ -34,7 +34,7 @@ EXPORTED = [
     "gx_batch_create", "gx_batch_run", "gx_batch_results", "gx_batch_instance_config",
     "gx_batch_destroy", "gx_explore_batch", "gx_autotune",
     "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_get_stats",
-    "gx_server_destroy",
+    "gx_server_destroy", "gx_network_add_monitor", "gx_monitored_network_free",
 ]
 
 
@@ -91,7 +91,20 @@ class _ExploreResult(ctypes.Structure):
                 ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32)),
                 ("local_duplicates", ctypes.c_uint64),
                 ("n_violations", ctypes.c_uint64), ("violations", ctypes.POINTER(ctypes.c_uint32)),
-                ("violation_level", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("violation_level", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("states", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class _Monitor(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_uint32), ("initial", ctypes.c_uint32),
+                ("n_trans", ctypes.c_uint32), ("src", ctypes.c_void_p),
+                ("action", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("bad", ctypes.c_void_p)]
+
+
+class _MonitoredNetwork(ctypes.Structure):
+    _fields_ = [("net", _Network), ("monitor_proc", ctypes.c_uint32),
+                ("monitor_bad", ctypes.POINTER(ctypes.c_uint8)), ("owner", ctypes.c_void_p)]
 
 
 class _BatchOpts(ctypes.Structure):
@@ -99,7 +112,8 @@ class _BatchOpts(ctypes.Structure):
                 ("max_hashes", ctypes.c_uint32), ("bucket_words", ctypes.c_uint32),
                 ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("max_levels", ctypes.c_uint32),
-                ("deadlock_capacity", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p)]
+                ("deadlock_capacity", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
+                ("keep_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -107,7 +121,7 @@ class _ServerOpts(ctypes.Structure):
                 ("max_hashes", ctypes.c_uint32), ("load_factor", ctypes.c_double),
                 ("hash_seed", ctypes.c_uint64), ("bucket_words", ctypes.c_uint32),
                 ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("keep_states", ctypes.c_uint32)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -146,6 +160,11 @@ def lib() -> ctypes.CDLL:
         L.gx_table_dump.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
         L.gx_table_read_raw.restype = st
         L.gx_table_read_raw.argtypes = [vp, vp, u64, u64]
+        L.gx_network_add_monitor.restype = st
+        L.gx_network_add_monitor.argtypes = [ctypes.POINTER(_Network), ctypes.POINTER(_Monitor),
+                                             ctypes.POINTER(_MonitoredNetwork)]
+        L.gx_monitored_network_free.restype = None
+        L.gx_monitored_network_free.argtypes = [ctypes.POINTER(_MonitoredNetwork)]
         L.gx_table_copy_raw.restype = st
         L.gx_table_copy_raw.argtypes = [vp, vp, u64, u64, vp]
         L.gx_hash_bucket.restype = st
@@ -362,6 +381,63 @@ class _NetHolder:
                           rules.ctypes.data if rules.size else None)
 
 
+@dataclass
+class Network:
+    """A network of LTSs as the library describes it (Sec. 3): per process its
+    state count, initial state and (src, label, dst) transitions, the label
+    count and the rule matrix (label per process or -1)."""
+    n_states: np.ndarray
+    initial: np.ndarray
+    trans: list
+    n_labels: int
+    rules: np.ndarray
+
+
+def add_monitor(net, automaton, bad) -> tuple:
+    """gx_network_add_monitor: the network with the automaton of a negated
+    safety property as its last process (Sec. 3).  ``automaton`` is
+    (n_states, initial, [(src, action, dst)]) with actions numbered as in
+    gx_monitor (rule r, or n_rules + l for label l fired alone); ``bad``
+    lists its bad states.  Returns (Network, monitor process, bad flags) for
+    explore(..., monitor=(process, flags))."""
+    n, init, trans = automaton
+    t = np.asarray(trans, dtype=np.uint32).reshape(-1, 3)
+    src, act, dst = (np.ascontiguousarray(t[:, i]) for i in range(3))
+    flags = np.zeros(max(1, int(n)), dtype=np.uint8)
+    flags[list(bad)] = 1
+    h = _NetHolder(net)
+    mon = _Monitor(int(n), int(init), t.shape[0], src.ctypes.data, act.ctypes.data,
+                   dst.ctypes.data, flags.ctypes.data)
+    out = _MonitoredNetwork()
+    _check(lib().gx_network_add_monitor(ctypes.byref(h.c), ctypes.byref(mon), ctypes.byref(out)),
+           "gx_network_add_monitor")
+    try:
+        c = out.net
+        P = int(c.n_procs)
+        n_states, initial, tr = [], [], []
+        for p in range(P):
+            lt = c.procs[p]
+            k = int(lt.n_trans)
+            cols = [np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_uint32)),
+                                          shape=(k,)).copy() if k else np.zeros(0, np.uint32)
+                    for ptr in (lt.src, lt.label, lt.dst)]
+            n_states.append(int(lt.n_states))
+            initial.append(int(lt.initial))
+            tr.append(np.stack(cols, axis=1).astype(np.uint32).reshape(-1, 3))
+        R = int(c.n_rules)
+        if R:
+            rules = np.ctypeslib.as_array(ctypes.cast(c.rules, ctypes.POINTER(ctypes.c_int32)),
+                                          shape=(R * P,)).copy().reshape(R, P)
+        else:
+            rules = np.zeros((0, P), np.int32)
+        badf = np.ctypeslib.as_array(out.monitor_bad, shape=(n_states[-1],)).astype(bool)
+        composed = Network(np.asarray(n_states, np.uint32), np.asarray(initial, np.uint32), tr,
+                           int(c.n_labels), rules)
+        return composed, int(out.monitor_proc), badf
+    finally:
+        lib().gx_monitored_network_free(ctypes.byref(out))
+
+
 def network_words(net) -> int:
     h = _NetHolder(net)
     w = ctypes.c_uint32()
@@ -390,6 +466,7 @@ class ExploreResult:
     local_duplicates: int = 0
     violations: np.ndarray = None  # (n, w) uint32, sorted (safety monitor)
     violation_level: int | None = None
+    states: np.ndarray = None  # (n_states, w) uint32, sorted (keep_states of batches, servers)
 
 
 def _take_result(res: _ExploreResult) -> ExploreResult:
@@ -404,8 +481,13 @@ def _take_result(res: _ExploreResult) -> ExploreResult:
     else:
         viol = np.zeros(0, np.uint32)
     vl = None if res.violation_level == 0xFFFFFFFF else int(res.violation_level)
+    states = None
+    if res.states:
+        states = np.ctypeslib.as_array(res.states, shape=(max(1, res.n_states * w),))
+        states = states[: res.n_states * w].copy().reshape(-1, w)
     out = ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
-                        dead.reshape(-1, w), int(res.local_duplicates), viol.reshape(-1, w), vl)
+                        dead.reshape(-1, w), int(res.local_duplicates), viol.reshape(-1, w), vl,
+                        states)
     lib().gx_explore_result_free(ctypes.byref(res))
     return out
 
@@ -452,7 +534,8 @@ class Batch:
 
     def __init__(self, nets, capacity, *, hash_seed: int = 0, max_hashes: int = 0,
                  bucket_words: int = 0, subgroup: int = 0, keys_per_subgroup: int = 0,
-                 use_graph: bool = False, max_levels: int = 0, deadlock_capacity: int = 0):
+                 use_graph: bool = False, max_levels: int = 0, deadlock_capacity: int = 0,
+                 keep_states: bool = False):
         self.n = len(nets)
         holders = [_NetHolder(net) for net in nets]
         arr = (_Network * self.n)(*[h.c for h in holders])
@@ -460,7 +543,8 @@ class Batch:
         if cap.shape[0] != self.n:
             raise ValueError("one capacity per network")
         opts = _BatchOpts(cap.ctypes.data, hash_seed, max_hashes, bucket_words, subgroup,
-                          keys_per_subgroup, int(use_graph), max_levels, deadlock_capacity, None)
+                          keys_per_subgroup, int(use_graph), max_levels, deadlock_capacity, None,
+                          int(keep_states), 0)
         h = ctypes.c_void_p()
         _check(lib().gx_batch_create(arr, self.n, ctypes.byref(opts), ctypes.byref(h)),
                "gx_batch_create")
@@ -511,9 +595,9 @@ class Server:
 
     def __init__(self, budget_bytes: int, *, max_active: int = 0, max_hashes: int = 0,
                  load_factor: float = 0.0, hash_seed: int = 0, bucket_words: int = 0,
-                 subgroup: int = 0, keys_per_subgroup: int = 0):
+                 subgroup: int = 0, keys_per_subgroup: int = 0, keep_states: bool = False):
         opts = _ServerOpts(budget_bytes, max_active, max_hashes, load_factor, hash_seed,
-                           bucket_words, subgroup, keys_per_subgroup, 0)
+                           bucket_words, subgroup, keys_per_subgroup, int(keep_states))
         h = ctypes.c_void_p()
         _check(lib().gx_server_create(ctypes.byref(opts), ctypes.byref(h)), "gx_server_create")
         self._h = h

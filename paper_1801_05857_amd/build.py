@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libgx.so")
 SOURCES = ["gx_table.hip", "gx_fop_s1.hip", "gx_fop_s2.hip", "gx_fop_s4.hip",
            "gx_explore.hip", "gx_explore_s1.hip", "gx_explore_s2.hip", "gx_explore_s4.hip",
            "gx_batch.hip", "gx_batch_s1.hip", "gx_batch_s2.hip", "gx_batch_s4.hip",
-           "gx_server.hip", "gx_serve_s1.hip", "gx_serve_s2.hip", "gx_serve_s4.hip"]
+           "gx_server.hip", "gx_serve_s1.hip", "gx_serve_s2.hip", "gx_serve_s4.hip",
+           "gx_network.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -42,7 +42,6 @@ extern template int batch_resident<4>(uint32_t, uint32_t, uint32_t, size_t);
 namespace {
 
 constexpr uint32_t kDefaultMaxLevels = 4096;
-constexpr uint32_t kQueuePerInstance = 512;
 constexpr uint64_t kSpinLimit = 1ull << 23;  // polls of one to two microseconds each
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -108,6 +107,8 @@ struct gx_batch {
   uint32_t H = 8;
   std::vector<uint32_t> w, cls;  // per instance: words, class index
   std::vector<uint32_t> Bi, Gi, Ui;
+  std::vector<uint64_t> tab_off, tab_words;  // per instance: its table partition in its class
+  bool keep_states = false;
   std::vector<Class> classes;
   hipEvent_t ev_fork = nullptr;
   bool use_graph = false;
@@ -319,6 +320,10 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
   }
   b->n = n;
   b->max_levels = opts->max_levels ? opts->max_levels : gx::kDefaultMaxLevels;
+  if (static_cast<uint64_t>(n) * b->max_levels >= (uint64_t(1) << 31)) {
+    delete b;
+    return GX_EINVAL;
+  }
   b->seed = opts->hash_seed ? opts->hash_seed : 0x1801058570ull;
   b->H = opts->max_hashes ? opts->max_hashes : 8;
   b->w = words;
@@ -326,6 +331,9 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
   b->Bi.resize(n);
   b->Gi.resize(n);
   b->Ui.resize(n);
+  b->tab_off.resize(n);
+  b->tab_words.resize(n);
+  b->keep_states = opts->keep_states != 0;
   // per-instance kernel configuration: explicit, else autotuned for the
   // instance's slot width at the load factor its capacity is declared for
   for (uint32_t i = 0; i < n; ++i) {
@@ -398,6 +406,8 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
       const uint64_t cap = opts->capacity[i];
       nb[k] = (cap + c.B / S - 1) / (c.B / S);
       tab_off[k] = tw;
+      b->tab_off[i] = tw;
+      b->tab_words[i] = nb[k] * c.B;
       tw += gx::align_up(nb[k] * c.B, 64);
       fr_off[k] = fw;
       fw += 2 * gx::align_up(cap * S, 64);
@@ -407,7 +417,9 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
     }
     c.table_words = tw;
     c.img_stride = static_cast<uint32_t>(gx::align_up(max_img, 4));
-    c.queue_cap = nc * gx::kQueuePerInstance;
+    // every instance publishes at most one entry per level, so the queue
+    // never overflows (checked against 2^31 entries when the batch is made)
+    c.queue_cap = nc * b->max_levels;
     uint64_t sum_cap = 0;
     for (uint32_t i : c.members) sum_cap += opts->capacity[i];
     c.dead_cap = opts->deadlock_capacity ? opts->deadlock_capacity
@@ -631,6 +643,14 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
       outs[i].level_counts = L;
       outs[i].n_deadlocks = dl.size();
       outs[i].deadlocks = D;
+      if (b->keep_states) {
+        const gx_status ks = gx::sorted_keys_malloc(c.tables + b->tab_off[i], b->tab_words[i], S,
+                                                    w, &outs[i].states);
+        if (ks != GX_OK) {
+          gx_explore_result_free(&outs[i]);
+          inst_status[i] = ks;
+        }
+      }
     }
   }
   return GX_OK;

@@ -347,9 +347,11 @@ void gx_explore_result_free(gx_explore_result* r) {
   std::free(r->level_counts);
   std::free(r->deadlocks);
   std::free(r->violations);
+  std::free(r->states);
   r->level_counts = nullptr;
   r->deadlocks = nullptr;
   r->violations = nullptr;
+  r->states = nullptr;
 }
 
 gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* opts,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "../../include/gx.h"
 #include "gx_device.hpp"
@@ -105,6 +106,15 @@ hipError_t launch_find_or_put(const gx_table* t, const uint32_t* keys, uint64_t 
 // (a kernel, never a memset node, so it may be captured in a graph).
 hipError_t fill_words(uint32_t* p, uint64_t n_words, uint32_t value, int device,
                       hipStream_t stream);
+
+// The keys stored in total_words words of bucket storage (slots of S words,
+// keys of w words) on the device, sorted lexicographically, w words each.
+// Waits for all device work.  *n_out receives the number of keys.
+gx_status sorted_keys(const uint32_t* dev_words, uint64_t total_words, uint32_t S, uint32_t w,
+                      std::vector<uint32_t>* out, uint64_t* n_out);
+// The same into a malloc'd array (for gx_explore_result.states).
+gx_status sorted_keys_malloc(const uint32_t* dev_words, uint64_t total_words, uint32_t S,
+                             uint32_t w, uint32_t** out);
 
 // Number of workgroups that keep every CU busy for a grid-stride kernel.
 uint32_t resident_grid(int device, uint32_t per_cu);

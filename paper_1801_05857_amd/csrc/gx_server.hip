@@ -89,6 +89,7 @@ struct gx_server {
   // configuration
   uint64_t budget = 0;
   uint32_t max_active = 0;
+  bool keep_states = false;
   double load = 0.5;
   uint64_t seed = 0;
   uint32_t H = 8;
@@ -273,7 +274,10 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
     std::sort(dl.begin(), dl.end());
     uint64_t* L = static_cast<uint64_t*>(std::malloc(sizeof(uint64_t) * j.levels.size()));
     uint32_t* D = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (n_dead * w + 1)));
+    uint32_t* V = nullptr;  // the table's contents, read before its block is released
     if (!L || !D) rs = GX_ENOMEM;
+    if (rs == GX_OK && s->keep_states)
+      rs = sorted_keys_malloc(j.t->words, j.t->n_buckets * j.t->B, S, w, &V);
     if (rs == GX_OK) {
       uint64_t total = 0;
       for (size_t l = 0; l < j.levels.size(); ++l) {
@@ -290,10 +294,12 @@ void finish_job(gx_server* s, size_t k, gx_status st, uint64_t transitions, uint
       r->result.n_deadlocks = n_dead;
       r->result.deadlocks = D;
       r->result.violation_level = 0xFFFFFFFFu;  // no safety monitor in the server
+      r->result.states = V;
       s->stats.states += total;
     } else {
       std::free(L);
       std::free(D);
+      std::free(V);
     }
     complete(s, r, rs);
   }
@@ -458,6 +464,7 @@ gx_status gx_server_create(const gx_server_opts* opts, gx_server** out) {
   if (!s) return GX_ENOMEM;
   s->budget = opts->budget_bytes;
   s->max_active = opts->max_active ? opts->max_active : 256;
+  s->keep_states = opts->keep_states != 0;
   s->load = load;
   s->seed = opts->hash_seed ? opts->hash_seed : 0x1801058570ull;
   s->H = opts->max_hashes ? opts->max_hashes : 8;

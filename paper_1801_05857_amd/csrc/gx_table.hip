@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -133,6 +134,75 @@ void free_table(gx_table* t) {
 
 // ====================================================================== ABI
 using gx::kEmpty;
+
+namespace gx {
+
+gx_status sorted_keys(const uint32_t* dev_words, uint64_t total_words, uint32_t S, uint32_t w,
+                      std::vector<uint32_t>* out, uint64_t* n_out) {
+  std::vector<uint32_t> raw;
+  try {
+    raw.resize(total_words);
+  } catch (...) {
+    return GX_ENOMEM;
+  }
+  if (hipDeviceSynchronize() != hipSuccess ||
+      (total_words && hipMemcpy(raw.data(), dev_words, total_words * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost) != hipSuccess))
+    return GX_EDEVICE;
+  const uint64_t n_slots = total_words / S;
+  uint64_t count = 0;
+  for (uint64_t s = 0; s < n_slots; ++s) count += raw[s * S] != kEmpty ? 1 : 0;
+  try {
+    out->resize(count * w);
+  } catch (...) {
+    return GX_ENOMEM;
+  }
+  if (w <= 2) {
+    std::vector<uint64_t> v;
+    v.reserve(count);
+    for (uint64_t s = 0; s < n_slots; ++s) {
+      if (raw[s * S] == kEmpty) continue;
+      uint64_t x = w == 1 ? raw[s] : (static_cast<uint64_t>(raw[s * 2]) << 32) | raw[s * 2 + 1];
+      v.push_back(x);  // word0 in the high half: numeric order is lexicographic
+    }
+    std::sort(v.begin(), v.end());
+    for (uint64_t i = 0; i < count; ++i) {
+      if (w == 1) {
+        (*out)[i] = static_cast<uint32_t>(v[i]);
+      } else {
+        (*out)[2 * i] = static_cast<uint32_t>(v[i] >> 32);
+        (*out)[2 * i + 1] = static_cast<uint32_t>(v[i]);
+      }
+    }
+  } else {
+    std::vector<std::array<uint32_t, 4>> v;
+    v.reserve(count);
+    for (uint64_t s = 0; s < n_slots; ++s) {
+      if (raw[s * 4] == kEmpty) continue;
+      v.push_back({raw[s * 4], raw[s * 4 + 1], raw[s * 4 + 2], w == 4 ? raw[s * 4 + 3] : 0u});
+    }
+    std::sort(v.begin(), v.end());
+    for (uint64_t i = 0; i < count; ++i)
+      for (uint32_t k = 0; k < w; ++k) (*out)[i * w + k] = v[i][k];
+  }
+  *n_out = count;
+  return GX_OK;
+}
+
+gx_status sorted_keys_malloc(const uint32_t* dev_words, uint64_t total_words, uint32_t S,
+                             uint32_t w, uint32_t** out) {
+  std::vector<uint32_t> keys;
+  uint64_t n = 0;
+  const gx_status st = sorted_keys(dev_words, total_words, S, w, &keys, &n);
+  if (st != GX_OK) return st;
+  uint32_t* p = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * (keys.size() + 1)));
+  if (!p) return GX_ENOMEM;
+  std::copy(keys.begin(), keys.end(), p);
+  *out = p;
+  return GX_OK;
+}
+
+}  // namespace gx
 
 extern "C" {
 
@@ -290,51 +360,13 @@ gx_status gx_table_copy_raw(gx_table* t, uint32_t* dev_words, uint64_t first, ui
 
 gx_status gx_table_dump(gx_table* t, uint32_t* host_keys, uint64_t cap, uint64_t* n_out) {
   if (!t || !n_out) return GX_EINVAL;
-  const uint64_t total = t->n_buckets * t->B;
-  std::vector<uint32_t> raw;
-  try {
-    raw.resize(total);
-  } catch (...) {
-    return GX_ENOMEM;
-  }
-  if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(raw.data(), t->words, total * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
-          hipSuccess)
-    return GX_EDEVICE;
-  const uint32_t S = t->S, w = t->w;
-  const uint64_t n_slots = total / S;
+  std::vector<uint32_t> keys;
   uint64_t count = 0;
-  for (uint64_t s = 0; s < n_slots; ++s) count += raw[s * S] != kEmpty ? 1 : 0;
+  const gx_status s = gx::sorted_keys(t->words, t->n_buckets * t->B, t->S, t->w, &keys, &count);
+  if (s != GX_OK) return s;
   *n_out = count;
   if (!host_keys || cap < count) return GX_ENOMEM;
-  if (w <= 2) {
-    std::vector<uint64_t> v;
-    v.reserve(count);
-    for (uint64_t s = 0; s < n_slots; ++s) {
-      if (raw[s * S] == kEmpty) continue;
-      uint64_t x = w == 1 ? raw[s] : (static_cast<uint64_t>(raw[s * 2]) << 32) | raw[s * 2 + 1];
-      v.push_back(x);  // word0 in the high half: numeric order is lexicographic
-    }
-    std::sort(v.begin(), v.end());
-    for (uint64_t i = 0; i < count; ++i) {
-      if (w == 1) {
-        host_keys[i] = static_cast<uint32_t>(v[i]);
-      } else {
-        host_keys[2 * i] = static_cast<uint32_t>(v[i] >> 32);
-        host_keys[2 * i + 1] = static_cast<uint32_t>(v[i]);
-      }
-    }
-  } else {
-    std::vector<std::array<uint32_t, 4>> v;
-    v.reserve(count);
-    for (uint64_t s = 0; s < n_slots; ++s) {
-      if (raw[s * 4] == kEmpty) continue;
-      v.push_back({raw[s * 4], raw[s * 4 + 1], raw[s * 4 + 2], w == 4 ? raw[s * 4 + 3] : 0u});
-    }
-    std::sort(v.begin(), v.end());
-    for (uint64_t i = 0; i < count; ++i)
-      for (uint32_t k = 0; k < w; ++k) host_keys[i * w + k] = v[i][k];
-  }
+  std::copy(keys.begin(), keys.end(), host_keys);
   return GX_OK;
 }
 

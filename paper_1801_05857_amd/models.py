@@ -141,79 +141,33 @@ def parse_par(text: str, files: dict) -> LoadedNetwork:
 
 
 def add_monitor(net, monitor: Lts, bad) -> tuple:
-    """Add the automaton of a negated safety property to a network (Sec. 3).
+    """Add the automaton of a negated safety property, given with action
+    names, to a network (Sec. 3), through gx_network_add_monitor.
 
     The automaton observes actions by name: the result label of a
-    synchronisation vector, or the label of a transition that a process fires
-    alone.  Every observed action then takes the automaton along: a vector
-    whose result it observes gains the automaton as a participant, and a
-    label that process p fires alone becomes a vector of p and the automaton.
-    Actions the automaton does not observe fire as before.  Readings: an
-    observed action that the automaton does not specify in some state leaves
-    it in that state (the automaton is completed with self-loops, so it
-    never blocks the network), and actions it names but the network never
-    performs are dropped.
+    synchronisation vector (``rule_names``), or a label (``labels``) that a
+    process fires alone; a name that is both stands for both actions.  Names
+    become the action numbers of gx_monitor (rule r; n_rules + l for label l
+    fired alone) and the library composes the network (see gx.h).  ``net``
+    needs ``n_states``, ``initial``, ``trans``, ``n_labels`` and ``rules``;
+    without ``labels`` / ``rule_names`` labels are named ``L<id>`` and vectors
+    ``R<index>``.  ``bad`` lists the automaton's bad states.  Returns (network
+    with the automaton as its last process, that process's index, per-state
+    bad flags)."""
+    from . import add_monitor as gx_add_monitor
 
-    ``net`` needs ``n_states``, ``initial``, ``trans``, ``n_labels`` and
-    ``rules``; its ``labels`` and ``rule_names``, when present, name actions
-    (otherwise labels are ``L<id>`` and vectors ``R<index>``).  ``bad`` lists
-    the automaton's bad states.  Returns (network with the automaton as its
-    last process, that process's index, per-state bad flags).
-    """
     P = len(net.n_states)
     rules = np.asarray(net.rules, dtype=np.int32).reshape(-1, P)
+    R = rules.shape[0]
     labels = list(getattr(net, "labels", None) or [f"L{i}" for i in range(net.n_labels)])
-    rule_names = list(getattr(net, "rule_names", None) or
-                      [f"R{r}" for r in range(rules.shape[0])])
     labels = labels + [f"L{i}" for i in range(len(labels), net.n_labels)]
-    index = {nm: i for i, nm in enumerate(labels)}
-
-    def lid(name: str) -> int:
-        if name not in index:
-            index[name] = len(labels)
-            labels.append(name)
-        return index[name]
-
-    alphabet = {lab for _, lab, _ in monitor.trans}
-    performed = set()
-    new_rules, names = [], []
-    for r in range(rules.shape[0]):
-        nm = rule_names[r]
-        obs = nm in alphabet
-        if obs:
-            performed.add(nm)
-        new_rules.append(list(rules[r]) + [lid(nm) if obs else -1])
-        names.append(nm)
-    for p in range(P):
-        governed = set(int(x) for x in rules[:, p] if x >= 0)
-        used = set(int(x) for x in np.asarray(net.trans[p], dtype=np.int64).reshape(-1, 3)[:, 1])
-        for lab in sorted(used - governed):
-            nm = labels[lab]
-            if nm in alphabet:
-                performed.add(nm)
-                row = [-1] * (P + 1)
-                row[p], row[P] = lab, lid(nm)
-                new_rules.append(row)
-                names.append(nm)
-    have = {(s_, a) for s_, a, _ in monitor.trans}
-    mt = [(s_, lid(a), d) for s_, a, d in monitor.trans if a in performed]
-    for m in range(monitor.n_states):
-        for a in sorted(performed):
-            if (m, a) not in have:
-                mt.append((m, lid(a), m))
-    bad_flags = np.zeros(monitor.n_states, dtype=bool)
-    bad_flags[list(bad)] = True
-    composed = LoadedNetwork(
-        n_states=np.append(np.asarray(net.n_states, np.uint32), np.uint32(monitor.n_states)),
-        initial=np.append(np.asarray(net.initial, np.uint32), np.uint32(monitor.initial)),
-        trans=[np.asarray(t, dtype=np.uint32).reshape(-1, 3) for t in net.trans] +
-              [np.asarray(mt, dtype=np.uint32).reshape(-1, 3)],
-        n_labels=max(1, len(labels)),
-        rules=np.asarray(new_rules, dtype=np.int32).reshape(-1, P + 1),
-        labels=labels,
-        rule_names=names,
-    )
-    return composed, P, bad_flags
+    rule_names = list(getattr(net, "rule_names", None) or [f"R{r}" for r in range(R)])
+    trans = []
+    for src, name, dst in monitor.trans:
+        trans += [(src, r, dst) for r in range(R) if rule_names[r] == name]
+        trans += [(src, R + l, dst) for l in range(net.n_labels) if labels[l] == name]
+    comp, mp, flags = gx_add_monitor(net, (monitor.n_states, monitor.initial, trans), bad)
+    return comp, mp, flags
 
 
 def write_aut(n_states: int, initial: int, trans) -> str:

@@ -18,3 +18,16 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return GOLDEN
+
+
+def read_pool(name):
+    """Rows of a pool golden file written by tests/golden/make_*.py: {index:
+    dict(words, states, transitions, deadlocks, dead_digest, levels)}."""
+    rows = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x) for x in line.split()]
+        rows[v[0]] = {"words": v[1], "states": v[2], "transitions": v[3], "deadlocks": v[4],
+                      "dead_digest": (v[5], v[6]), "levels": v[7:]}
+    return rows

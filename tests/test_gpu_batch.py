@@ -1,11 +1,16 @@
 """GPU parity of batched exploration (many networks in one persistent launch
-per kernel class) against the oracle BFS, instance by instance, bit-exact."""
+per kernel class) against the oracle BFS, instance by instance, bit-exact:
+counts, levels, deadlocks and (keep_states) every instance's table contents;
+the benchmarked 1024-network batch against the oracle's results of all its
+instances (tests/golden/batch_1024_s11.txt)."""
 import numpy as np
 import pytest
 
 import oracle
 import paper_1801_05857_amd as gx
 import workloads as W
+
+from conftest import read_pool
 
 torch = pytest.importorskip("torch")
 
@@ -38,11 +43,11 @@ def _mixed_networks(k):
 @pytest.fixture(scope="module")
 def mixed():
     nets = _mixed_networks(28)
-    want = [oracle.explore(n) for n in nets]
+    want = [oracle.explore(n, want_visited=True) for n in nets]
     return nets, want
 
 
-def _check(res, want):
+def _check(res, want, states=False):
     assert len(res) == len(want)
     for k, ((st, got), ref) in enumerate(zip(res, want)):
         assert st == gx.GX_OK, (k, gx.status_str(st))
@@ -50,18 +55,50 @@ def _check(res, want):
         assert got.levels.tolist() == ref.levels.tolist(), k
         assert got.n_transitions == ref.n_transitions, k
         assert np.array_equal(got.deadlocks, ref.deadlocks), k
+        if states:  # the instance's table holds exactly the reachable set
+            assert np.array_equal(got.states, ref.visited), k
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_matches_oracle(dev, mixed, use_graph):
     nets, want = mixed
     cap = [max(64, 3 * r.n_states) for r in want]
-    with gx.Batch(nets, cap, use_graph=use_graph, max_hashes=32) as b:
+    with gx.Batch(nets, cap, use_graph=use_graph, max_hashes=32, keep_states=True) as b:
         b.run()
-        _check(b.results(), want)
+        _check(b.results(), want, states=True)
         # a second run resets every table and repeats the batch
         b.run()
-        _check(b.results(), want)
+        _check(b.results(), want, states=True)
+
+
+def test_benchmarked_batch_matches_oracle(dev):
+    """The 1024-network batch exactly as the benchmark runs it (capacities
+    twice the live-state products, autotuned configurations, hipGraph,
+    16 hash functions): every instance equals the oracle's exploration."""
+    nets, bounds = W.batch_networks(1024, 11)
+    want = read_pool("batch_1024_s11.txt")
+    with gx.Batch(nets, [2 * c for c in bounds], use_graph=True, max_hashes=16) as b:
+        b.run()
+        res = b.results()
+    for i, (st, got) in enumerate(res):
+        ref = want[i]
+        assert st == gx.GX_OK, (i, gx.status_str(st))
+        assert got.n_states == ref["states"], i
+        assert got.levels.tolist() == ref["levels"], i
+        assert got.n_transitions == ref["transitions"], i
+        assert len(got.deadlocks) == ref["deadlocks"], i
+        assert oracle.digest(got.deadlocks, got.words_per_state) == ref["dead_digest"], i
+
+
+def test_batch_deeper_than_512_levels(dev):
+    """A single 1500-state cycle: 1500 BFS levels, one queue entry each."""
+    net = W.independent_cycles((1500,))
+    want = oracle.explore(net, want_visited=True)
+    assert len(want.levels) == 1500
+    _check(gx.explore_batch([net], [4096], max_hashes=32), [want])
+    # more levels than max_levels: the instance reports GX_ENOMEM
+    res = gx.explore_batch([net], [4096], max_hashes=32, max_levels=1000)
+    assert res[0][0] == gx.GX_ENOMEM
 
 
 def test_batch_degenerate_networks(dev):

@@ -1,12 +1,17 @@
 """GPU parity of gx_explore against the oracle BFS: reachable-state count,
 per-level counts, transition count, deadlock set and the final table contents,
 all bit-exact."""
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import paper_1801_05857_amd as gx
 import workloads as W
+
+from conftest import GOLDEN
+from setdigest import table_digest
 
 torch = pytest.importorskip("torch")
 
@@ -19,6 +24,15 @@ def dev():
         pytest.skip("no GPU")
     gx.lib()
     return torch.device("cuda:0")
+
+
+def _read_rows(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            rows.append(tuple(int(x) for x in line.split()))
+    return rows
 
 
 def _explore_and_compare(net, B=32, G=0, cap=None, check_dump=True, **kw):
@@ -56,6 +70,38 @@ def test_tiny_cycles_config(dev):
 def test_token_ring(dev, n):
     got = _explore_and_compare(W.token_ring(n), B=32)
     assert got.n_states == 2 * n * 3 ** (n - 1)
+
+
+def _ring_golden():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "token_ring_13_15.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x) for x in line.split()]
+        rows[v[0]] = {"states": v[1], "transitions": v[2], "deadlocks": v[3],
+                      "digest": (v[4], v[5]), "levels": v[6:]}
+    return rows
+
+
+@pytest.mark.parametrize("n", [13, 14, 15, 16])
+def test_token_ring_large(dev, n):
+    """Table 1 (right) beyond the hash-set oracle's reach: the state count
+    printed in the paper (13..16 nodes, two-word vectors); for 13..15 nodes
+    also every level count, the transition count and the digest of the
+    table's contents from the oracle's dense BFS."""
+    printed = dict(_read_rows("token_ring_table1.txt"))
+    net = W.token_ring(n)
+    with gx.Table(2, 16, 2 * printed[n], subgroup=4, keys_per_subgroup=1, max_hashes=32) as t:
+        got = gx.explore(net, t)
+        assert got.n_states == printed[n] == 2 * n * 3 ** (n - 1)
+        assert len(got.deadlocks) == 0
+        assert int(got.levels.sum()) == got.n_states
+        assert t.stats().stored == got.n_states
+        if n <= 15:
+            ref = _ring_golden()[n]
+            assert got.levels.tolist() == ref["levels"]
+            assert got.n_transitions == ref["transitions"]
+            assert table_digest(t, dev) == (ref["states"], ref["digest"])
 
 
 @pytest.mark.parametrize("name", ["lone", "selfloop", "ones", "never", "chain"])

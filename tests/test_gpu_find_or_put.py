@@ -15,6 +15,8 @@ import oracle
 import paper_1801_05857_amd as gx
 import workloads as W
 
+from setdigest import P, digest_words, table_digest
+
 torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
@@ -109,7 +111,7 @@ def test_specialisation_parity(dev, w, B, G, U):
         s = t.stats()
         assert s.stored == len(ref) and s.full == 0 and s.invalid == 0
         assert s.lookups == keys.shape[0] + batch2.shape[0]
-        if (G, U) in ((8, 1), (64, 4)):
+        if (G, U) in ((8, 1), (64, 4), (4, 1)):
             _placement_ok(t, dump)
 
 
@@ -240,11 +242,14 @@ def test_load_factor_09_needs_long_sequences(dev):
         assert t.dump().shape[0] == n
 
 
-@pytest.mark.parametrize("B,G,U", [(16, 16, 4)])
+@pytest.mark.parametrize("B,G,U", [(32, 4, 1), (16, 4, 1), (16, 16, 4)])
 def test_full_size_microbenchmark_properties(dev, B, G, U):
-    """The 2^28-key, 2^27-distinct stream at load factor 0.5 in the launch
-    configuration the benchmark times: exact NEW count, exactly one NEW per
-    distinct key, every key findable afterwards, and fresh keys still NEW."""
+    """The 2^28-key, 2^27-distinct stream at load factor 0.5, first in the
+    launch configuration the benchmark times (buckets of 32 words, 4-lane
+    subgroups, one key in flight): exact NEW count, exactly one NEW per
+    distinct key, the table holds exactly the distinct keys (count and set
+    digest: the stream holds every distinct key twice, so its digest is twice
+    the set's), every key findable afterwards, and fresh keys still NEW."""
     n_distinct = 1 << 27
     keys, idx = W.duplicated_stream_torch(n_distinct, 2, 1801058570, dev)
     with gx.Table(2, B, 2 * n_distinct, subgroup=G, keys_per_subgroup=U) as t:
@@ -259,6 +264,10 @@ def test_full_size_microbenchmark_properties(dev, B, G, U):
         del per_key
         s = t.stats()
         assert s.stored == n_distinct and s.full == 0
+        n_tab, d_tab = table_digest(t, dev)
+        d_stream = digest_words(keys.to(torch.int64) & 0xFFFFFFFF, 2)
+        assert n_tab == n_distinct
+        assert d_stream == ((2 * d_tab[0]) % P, (2 * d_tab[1]) % P)
         # a sample of stored keys is found; a sample of fresh keys is new
         sample = keys[:: 1 << 8].contiguous()
         st2 = torch.empty(sample.shape[0], dtype=torch.uint8, device=dev)

@@ -9,6 +9,8 @@ import oracle
 import paper_1801_05857_amd as gx
 import workloads as W
 
+from conftest import read_pool
+
 torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
@@ -42,7 +44,7 @@ def _nets():
 @pytest.fixture(scope="module")
 def reqs():
     nets = _nets()
-    return nets, [oracle.explore(n) for n in nets]
+    return nets, [oracle.explore(n, want_visited=True) for n in nets]
 
 
 def _same(got, ref):
@@ -54,12 +56,14 @@ def _same(got, ref):
 
 def test_served_mix_equals_oracle(dev, reqs):
     nets, want = reqs
-    with gx.Server(8 << 30, max_hashes=32) as srv:
+    with gx.Server(8 << 30, max_hashes=32, keep_states=True) as srv:
         ids = [srv.submit(n, max(16, 2 * r.n_states)) for n, r in zip(nets, want)]
         for rid, ref in zip(ids, want):
             st, got, lat = srv.poll(rid)
             assert st == gx.GX_OK
             _same(got, ref)
+            # the request's table held exactly the reachable set
+            assert np.array_equal(got.states, ref.visited)
             assert lat > 0
         s = srv.stats()
         assert s["completed"] == len(nets) and s["failed"] == 0
@@ -116,3 +120,38 @@ def test_poll_without_wait(dev):
         while r is None:
             r = srv.poll(rid, wait=False)
         assert r[0] == gx.GX_OK and r[1].n_states == 118098
+
+
+def test_served_pool_sample_matches_oracle(dev):
+    """Requests of the served workload's pool (random networks, 1- to 4-word
+    vectors, each declaring the product of its live-state counts), a seeded
+    sample of 48 of those up to 2e7 states submitted at once, each result
+    against the oracle's (tests/golden/served_pool.txt), then the same
+    requests one at a time: each result is the same alone and in the mix."""
+    nets, _, bounds = W.served_networks(256, 5)
+    want = read_pool("served_pool.txt")
+    small = [i for i in range(256) if want[i]["states"] <= 20_000_000]
+    rng = W.SplitMix64(48)
+    pick = [small[rng.below(len(small))] for _ in range(48)]
+    assert {want[i]["words"] for i in pick} == {1, 2, 3, 4}
+
+    def check(st, got, ref):
+        assert st == gx.GX_OK
+        assert got.n_states == ref["states"]
+        assert got.levels.tolist() == ref["levels"]
+        assert got.n_transitions == ref["transitions"]
+        assert len(got.deadlocks) == ref["deadlocks"]
+        assert oracle.digest(got.deadlocks, got.words_per_state) == ref["dead_digest"]
+
+    with gx.Server(64 << 30, max_hashes=16) as srv:
+        ids = [srv.submit(nets[i], bounds[i]) for i in pick]
+        mix = []
+        for rid, i in zip(ids, pick):
+            st, got, _ = srv.poll(rid)
+            check(st, got, want[i])
+            mix.append(got)
+        assert srv.stats()["active_peak"] > 1
+        for i, m in zip(pick[:12], mix[:12]):
+            st, got, _ = srv.poll(srv.submit(nets[i], bounds[i]))
+            check(st, got, want[i])
+            assert np.array_equal(got.deadlocks, m.deadlocks)

@@ -163,3 +163,33 @@ def test_digest_is_order_independent_and_sensitive():
     bad = st.copy()
     bad[5] = bad[6]
     assert oracle.digest(bad, 3) != d
+
+
+@pytest.mark.parametrize("name", ["batch_1024_s11.txt", "served_pool.txt"])
+def test_pool_golden_files_are_consistent(name):
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from conftest import read_pool
+
+    rows = read_pool(name)
+    assert len(rows) in (1024, 256)
+    for i, r in rows.items():
+        assert sum(r["levels"]) == r["states"] and r["levels"][0] == 1, (name, i)
+        assert r["deadlocks"] > 0 or r["dead_digest"] == (0, 0)
+    # a few rows recomputed by the hash-set oracle
+    nets = (W.batch_networks(1024, 11)[0] if name.startswith("batch")
+            else W.served_networks(256, 5)[0])
+    small = sorted((r["states"], i) for i, r in rows.items())[:5]
+    for _, i in small:
+        a = oracle.explore(nets[i])
+        assert a.levels.tolist() == rows[i]["levels"] and a.n_transitions == rows[i]["transitions"]
+
+
+def test_token_ring_golden_matches_table1(golden_dir):
+    printed = dict(_read_table("token_ring_table1.txt"))
+    for line in open(os.path.join(golden_dir, "token_ring_13_15.txt")):
+        if line.startswith("#"):
+            continue
+        v = [int(x) for x in line.split()]
+        assert v[1] == printed[v[0]] == sum(v[6:])
+        assert v[3] == 0  # no deadlocks

@@ -458,22 +458,23 @@ def served_networks(n: int, seed: int, log10_lo: float = 4.0, log10_hi: float = 
 
     Request i: a target T ~ log-uniform [10^lo, 10^hi] and a width w ~ U{1..4}
     words; P processes of 64 declared states (6-bit fields, five per word),
-    P ~ U{5(w-1)+1 .. 5w} raised until 64^P >= 4T; live counts m_p
-    (1 <= m_p <= 64) raised round-robin while prod m_p <= 4T.  Every reachable
-    local state is live, so prod m_p bounds the reachable set.  The declared
-    bound of a request is 2T.  Returns (networks, targets)."""
+    P ~ U{5(w-1)+1 .. 5w} raised until 64^P >= 2T; live counts m_p
+    (1 <= m_p <= 64) raised round-robin while prod m_p <= 2T (a third to all
+    of the product is reachable, so reachable sizes centre on T).  Every
+    reachable local state is live, so prod m_p bounds the reachable set; it
+    is the request's declared bound.  Returns (networks, targets, bounds)."""
     import math
 
     rng = SplitMix64(seed)
-    nets, targets = [], []
+    nets, targets, bounds = [], [], []
     for i in range(n):
         u = rng.next() / 2.0**64
         target = 10 ** (log10_lo + (log10_hi - log10_lo) * u)
         w = 1 + rng.below(4)
         P = 5 * (w - 1) + 1 + rng.below(5)
-        while 64 ** P < 4 * target and P < 5 * w:
+        while 64 ** P < 2 * target and P < 5 * w:
             P += 1
-        want = 4.0 * target
+        want = 2.0 * target
         m = [1] * P
         grew = True
         while grew:
@@ -485,4 +486,5 @@ def served_networks(n: int, seed: int, log10_lo: float = 4.0, log10_hi: float = 
         nets.append(random_lts(seed * 1000003 + i, P, 64, m, out_degree, 32, 0.25, 0.05,
                                name=f"served_{seed}_{i}"))
         targets.append(int(target))
-    return nets, targets
+        bounds.append(int(math.prod(m)))
+    return nets, targets, bounds
