@@ -374,17 +374,14 @@ def _mix62_torch(x):
 
 def duplicated_stream_torch(n_distinct: int, dup: int, seed: int, device, w: int = 2):
     """``duplicated_stream(n_distinct, dup, w, seed)`` generated with torch on
-    ``device`` (w = 1 or 2, n_distinct * dup a power of two).  Returns the
-    (n, w) int32 key tensor and the int64 tensor of distinct-key indices per
-    position."""
+    ``device`` (w = 1 or 2).  Returns the (n, w) int32 key tensor and the
+    int64 tensor of distinct-key indices per position."""
     import torch
 
     if w not in (1, 2):
         raise ValueError("one- or two-word keys")
 
     n = n_distinct * dup
-    if n & (n - 1):
-        raise ValueError("n_distinct * dup must be a power of two")
     bits = max(1, (n - 1).bit_length())
     mask = (1 << bits) - 1
     rng = SplitMix64(seed ^ 0x5EED5EED5EED5EED)
@@ -392,11 +389,19 @@ def duplicated_stream_torch(n_distinct: int, dup: int, seed: int, device, w: int
     def i64(c):
         return c - (1 << 64) if c >= (1 << 63) else c
 
-    y = torch.arange(n, dtype=torch.int64, device=device)
-    for _ in range(3):
-        a, b = rng.next() | 1, rng.next()
-        y = (y * i64(a) + i64(b)) & mask
-        y = y ^ (y >> max(1, bits // 2))
+    consts = [(rng.next() | 1, rng.next()) for _ in range(3)]
+
+    def permute(y):  # the seeded bijection of [0, 2^bits) of permutation()
+        for a, b in consts:
+            y = (y * i64(a) + i64(b)) & mask
+            y = y ^ (y >> max(1, bits // 2))
+        return y
+
+    y = permute(torch.arange(n, dtype=torch.int64, device=device))
+    bad = y >= n
+    while bool(bad.any()):  # cycle-walk back into [0, n)
+        y[bad] = permute(y[bad])
+        bad = y >= n
     idx = y % n_distinct
     c = (idx + (seed & MASK62)) & MASK62
     if w == 1:
