@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--serve-n", type=int, default=1000, help="requests per rate")
     ap.add_argument("--tiny", action="store_true",
                     help="only the tiny configuration")
+    ap.add_argument("--explore-large", action="store_true",
+                    help="only the large plain-path exploration (3.3e9 states)")
     ap.add_argument("--dup-sweep", action="store_true",
                     help="isolated insertion of 2^27 one-word keys at duplication 1..100")
     ap.add_argument("--token-ring", action="store_true",
@@ -247,6 +249,10 @@ def run_tiny(gx, torch, W, reps=10):
     times.sort()
     return {"workload": "tiny: 4 cyclic processes of 8 states, 2 rendezvous, w=1, table 2^16 words",
             "states": r.n_states, "levels": len(r.levels),
+            # the closed form: 8^4 states, 21 levels, 4 tau steps everywhere plus
+            # 2 x 64 joint jumps
+            "matches_closed_form": (r.n_states, len(r.levels), r.n_transitions) == (4096, 21,
+                                                                                     16512),
             "us_per_explore": round(times[len(times) // 2] * 1e6, 1)}
 
 
@@ -723,6 +729,9 @@ def main():
         return
     if args.tiny:
         print(json.dumps(run_tiny(gx, torch, W)), flush=True)
+        return
+    if args.explore_large:
+        print(json.dumps(run_explore_leg(gx, torch, W)), flush=True)
         return
     if args.explore:
         for spec in args.net or ["1:12:64:5:3:0.2"]:

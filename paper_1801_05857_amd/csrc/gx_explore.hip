@@ -16,6 +16,11 @@
 // compacted frontier, so no scan of the table is needed.  With a safety
 // monitor, every completed level is scanned once for states whose monitor
 // process is in a bad state.
+//
+// Levels of at most kSmallMaxLevel states (the first levels of every
+// exploration, the last ones of most, all of a small one) are instead
+// expanded by small_levels_kernel on one workgroup, up to kSmallLevels of
+// them per launch with no host round trip in between.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,7 +30,7 @@
 #include <cstring>
 #include <vector>
 
-#include "gx_explore_kernel.hpp"
+#include "gx_small_kernel.hpp"
 
 namespace gx {
 // instantiated in gx_explore_s1.hip, gx_explore_s2.hip and gx_explore_s4.hip
@@ -38,6 +43,9 @@ extern template hipError_t append_b<2>(uint32_t, uint32_t, uint32_t, const Appen
                                        hipStream_t);
 extern template hipError_t append_b<4>(uint32_t, uint32_t, uint32_t, const AppendArgs&, uint32_t,
                                        hipStream_t);
+extern template hipError_t launch_small<1>(uint32_t, const SmallArgs&, hipStream_t);
+extern template hipError_t launch_small<2>(uint32_t, const SmallArgs&, hipStream_t);
+extern template hipError_t launch_small<4>(uint32_t, const SmallArgs&, hipStream_t);
 }  // namespace gx
 
 namespace gx {
@@ -391,9 +399,11 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
                  stream, img_stride) != hipSuccess)
       return GX_ENOMEM;
   }
+  // the level's counters, then what a small-level launch reports
   constexpr size_t kCtrWords = gx::kCtrCount * gx::kCtrSpread;
-  if (!eb.ctr && (hipMalloc(&eb.ctr, kCtrWords * sizeof(uint64_t)) != hipSuccess ||
-                  hipHostMalloc(&eb.ctr_host, kCtrWords * sizeof(uint64_t)) != hipSuccess ||
+  constexpr size_t kBlockWords = kCtrWords + sizeof(gx::SmallOut) / sizeof(uint64_t);
+  if (!eb.ctr && (hipMalloc(&eb.ctr, kBlockWords * sizeof(uint64_t)) != hipSuccess ||
+                  hipHostMalloc(&eb.ctr_host, kBlockWords * sizeof(uint64_t)) != hipSuccess ||
                   hipMalloc(&eb.status, 8) != hipSuccess ||
                   hipMalloc(&eb.key, 4 * sizeof(uint32_t)) != hipSuccess)) {
     (void)hipGetLastError();
@@ -402,30 +412,47 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   for (int k = 0; k < 2; ++k)
     if ((s = grow_buf(&eb.f[k], &eb.f_cap[k], 1, 0, max_cap)) != GX_OK) return s;
   if ((s = grow_buf(&eb.dead, &eb.dead_cap, 1, 0, max_dead)) != GX_OK) return s;
+  // Small levels run on one workgroup (small_levels_kernel) when a level of
+  // `small_limit` states has room for all its successors in the frontier and
+  // successor buffers as they are; not with a safety monitor or the local
+  // duplicate filter, whose per-level work stays on the host path.
+  const bool dedup = opts && opts->local_dedup;
+  uint64_t small_limit = 0;
+  if (!monitor && !dedup) {
+    if ((s = grow_buf(&eb.succ, &eb.succ_cap, 1, 0, ~0ull)) != GX_OK) return s;
+    const uint64_t room = std::min<uint64_t>(
+        std::min<uint64_t>(eb.f_cap[0], eb.f_cap[1]),
+        std::min<uint64_t>(eb.succ_cap, max_cap));
+    small_limit = std::min<uint64_t>(gx::kSmallMaxLevel, room / max_succ);
+  }
 
   uint32_t init[4] = {0, 0, 0, 0};
   gx::pack_host(ni, ni.initial.data(), init);
   // the level's counters, spread over cache lines on the device, read back
   // into pinned host memory
   uint64_t* ctr_raw = eb.ctr_host;
-  std::memset(ctr_raw, 0, kCtrWords * sizeof(uint64_t));
+  std::memset(ctr_raw, 0, kBlockWords * sizeof(uint64_t));
+  const gx::SmallOut* small_out = reinterpret_cast<const gx::SmallOut*>(ctr_raw + kCtrWords);
   auto ctr = [&](uint32_t k) { return ctr_raw[k * gx::kCtrSpread]; };
   if (hipMemcpyAsync(eb.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
                      stream) != hipSuccess ||
       hipMemcpyAsync(eb.f[0], init, state_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(eb.key, init, t->w * sizeof(uint32_t), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
-      hipMemsetAsync(eb.ctr, 0, kCtrWords * sizeof(uint64_t), stream) != hipSuccess)
+      hipMemsetAsync(eb.ctr, 0, kBlockWords * sizeof(uint64_t), stream) != hipSuccess)
     return GX_EDEVICE;
-  // the initial state must be new, i.e. the table must not hold it yet
-  if (gx::launch_find_or_put(t, eb.key, 1, eb.status, nullptr, stream) != hipSuccess)
-    return GX_EDEVICE;
-  uint8_t st0 = 0;
-  if (hipMemcpyAsync(&st0, eb.status, 1, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
-    return GX_EDEVICE;
-  if (st0 == gx::kFull) return GX_ETABLEFULL;
-  if (st0 != gx::kNew) return GX_EINVAL;
+  // the initial state must be new, i.e. the table must not hold it yet (with
+  // small levels, the first small launch inserts it)
+  if (small_limit == 0) {
+    if (gx::launch_find_or_put(t, eb.key, 1, eb.status, nullptr, stream) != hipSuccess)
+      return GX_EDEVICE;
+    uint8_t st0 = 0;
+    if (hipMemcpyAsync(&st0, eb.status, 1, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return GX_EDEVICE;
+    if (st0 == gx::kFull) return GX_ETABLEFULL;
+    if (st0 != gx::kNew) return GX_EINVAL;
+  }
 
   // Safety monitor: a bitmask of the bad local states of the monitor
   // process; every completed level is scanned for states holding one.  The
@@ -489,7 +516,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, t->device);
   auto read_ctr = [&]() -> gx_status {
-    if (hipMemcpyAsync(ctr_raw, eb.ctr, kCtrWords * sizeof(uint64_t), hipMemcpyDeviceToHost,
+    if (hipMemcpyAsync(ctr_raw, eb.ctr, kBlockWords * sizeof(uint64_t), hipMemcpyDeviceToHost,
                        stream) !=
             hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
@@ -512,7 +539,59 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   constexpr uint64_t kTargetSlice = 1u << 22;  // 16384 workgroups per launch
   constexpr uint64_t kMaxRoom = 1ull << 28;    // states of frontier room one slice may claim
   uint64_t slice_no = 0;  // successor counters alternate from slice to slice
+  bool init_inserted = small_limit == 0;
   while (n_in > 0 && !stop) {
+    bool small = n_in <= small_limit;
+    if (small && std::min<uint64_t>(eb.dead_cap, max_dead) - dead_known < n_in) {
+      // every state of a small level may be a deadlock: room for a level
+      s = grow_buf(&eb.dead, &eb.dead_cap, std::min<uint64_t>(dead_known + n_in, max_dead),
+                   dead_known, max_dead);
+      if (s != GX_OK && s != GX_ENOMEM) return s;
+      small = std::min<uint64_t>(eb.dead_cap, max_dead) - dead_known >= n_in;
+    }
+    if (small) {
+      // small levels on one workgroup, as many as stay small (up to
+      // kSmallLevels per launch), then one read-back
+      gx::SmallArgs sa;
+      sa.t = t->dev();
+      sa.img = eb.img;
+      sa.img_words = img_words;
+      sa.img_stride = img_stride;
+      sa.f[0] = eb.f[0];
+      sa.f[1] = eb.f[1];
+      sa.f_cap = std::min<uint64_t>(std::min<uint64_t>(eb.f_cap[0], eb.f_cap[1]), max_cap);
+      sa.cur = static_cast<uint32_t>(cur);
+      sa.n_in = n_in;
+      sa.succ = eb.succ;
+      sa.succ_cap = eb.succ_cap;
+      sa.dead = eb.dead;
+      sa.dead_cap = std::min<uint64_t>(eb.dead_cap, max_dead);
+      sa.ctr = eb.ctr;
+      sa.out = reinterpret_cast<gx::SmallOut*>(eb.ctr + kCtrWords);
+      sa.limit = small_limit;
+      sa.init_key = init_inserted ? nullptr : eb.key;
+      hipError_t e = hipErrorInvalidValue;
+      switch (S) {
+        case 1: e = gx::launch_small<1>(t->B, sa, stream); break;
+        case 2: e = gx::launch_small<2>(t->B, sa, stream); break;
+        case 4: e = gx::launch_small<4>(t->B, sa, stream); break;
+      }
+      if (e != hipSuccess) return GX_EDEVICE;
+      s = read_ctr();
+      if (!init_inserted) {
+        init_inserted = true;
+        if (small_out->init_status == gx::kFull) return GX_ETABLEFULL;
+        if (small_out->init_status != gx::kNew) return GX_EINVAL;
+      }
+      if (s != GX_OK) return s;
+      for (uint64_t k = 0; k < small_out->n_levels; ++k) levels.push_back(small_out->levels[k]);
+      dead_known = ctr(gx::kCtrDead);
+      if (dead_known > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;
+      n_in = small_out->n_in;
+      cur = static_cast<int>(small_out->cur);
+      if (small_out->n_levels == 0 && n_in > 0) return GX_EDEVICE;  // no progress
+      continue;
+    }
     const int nxt = cur ^ 1;
     uint64_t tail_known = 0, bound = 0, dead_bound = dead_known, pos = 0;
     while (pos < n_in) {

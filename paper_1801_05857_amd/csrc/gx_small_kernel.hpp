@@ -1,0 +1,229 @@
+// Small BFS levels expanded on one workgroup, level after level, with no host
+// round trip between them: the device-side level loop of gx_explore for the
+// levels too small to fill the device (Sec. 5.2 traces the low rate on small
+// instances to small search layers and per-layer overhead).
+#pragma once
+
+#include <cstdint>
+
+#include "gx_explore_kernel.hpp"
+
+namespace gx {
+
+constexpr uint32_t kSmallThreads = 1024;  // one workgroup of 16 wavefronts
+constexpr uint32_t kSmallWaves = kSmallThreads / 64;
+constexpr uint32_t kSmallLevels = 64;     // levels one launch may complete
+constexpr uint64_t kSmallMaxLevel = 4096; // largest level the workgroup expands
+
+// What a launch leaves for the host (read back with the level counters).
+struct SmallOut {
+  uint64_t n_levels;     // levels completed by this launch; their sizes follow
+  uint64_t n_in;         // size of the current level (0: the exploration is over)
+  uint64_t cur;          // the frontier buffer holding it
+  uint64_t init_status;  // find-or-put status of the initial state (when inserted)
+  uint64_t pad[4];
+  uint64_t levels[kSmallLevels];
+};
+
+struct SmallArgs {
+  TableDev t;
+  const uint32_t* img;  // network image (global; copied to LDS)
+  uint32_t img_words;
+  uint32_t img_stride;
+  uint32_t* f[2];       // the two frontier buffers
+  uint64_t f_cap;       // states each holds
+  uint32_t cur;         // buffer holding the current level
+  uint64_t n_in;        // its size
+  uint32_t* succ;       // a level's successors, S words each
+  uint64_t succ_cap;
+  uint32_t* dead;
+  uint64_t dead_cap;
+  uint64_t* ctr;        // the exploration's counters (see ctr_at)
+  SmallOut* out;
+  uint64_t limit;       // largest level this launch expands (limit * max_succ fits)
+  const uint32_t* init_key;  // non-null: find-or-put it first (the level-0 state)
+};
+
+// Every level: (1) the workgroup numbers the level's successors state by
+// state (block prefix sum of the per-state counts) and writes them to the
+// successor buffer with the coalesced lockstep walk of emit_window; (2) all
+// sixteen wavefronts find-or-put those successors, gathering NEW ones per
+// wavefront in LDS and appending them to the next frontier with one atomic
+// add per flush; (3) thread 0 reads the level's size and decides: next level,
+// done, or back to the host (a level above the limit, a full table, the
+// deadlock buffer short of a level, or kSmallLevels levels done).  Probes use
+// the table's bucket size with (G, U) of this kernel: the claim protocol does
+// not depend on how many lanes read a bucket, and a workgroup on its own
+// needs every lane's key in flight to hide the probe latency.
+template <int S, int B, int G, int U>
+__global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a) {
+  extern __shared__ uint32_t smem[];
+  __shared__ uint32_t wave_tot[kSmallWaves];
+  __shared__ uint64_t sh_n_in;
+  __shared__ uint32_t sh_cur, sh_go, sh_levels;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = tid >> 6;
+  const int lane = __lane_id();
+  uint32_t* img = smem;
+  uint32_t* gbuf = smem + a.img_stride + wave * kAppendKeys * S;
+  for (uint32_t k = tid; k < a.img_words; k += kSmallThreads) img[k] = a.img[k];
+  if (tid == 0) {
+    const uint64_t dead = __hip_atomic_load(ctr_at(a.ctr, kCtrDead), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    sh_n_in = a.n_in;
+    sh_cur = a.cur;
+    sh_go = a.n_in > 0 && a.n_in <= a.limit && a.n_in <= a.dead_cap - min(dead, a.dead_cap)
+                ? 1u
+                : 0u;
+    sh_levels = 0;
+    // a level completed by the host path leaves its size in the tail
+    __hip_atomic_store(ctr_at(a.ctr, kCtrTail), 0ull, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  LaneStats st;
+  if (a.init_key != nullptr && wave == 0) {
+    uint32_t key[S];
+#pragma unroll
+    for (int x = 0; x < S; ++x) key[x] = lane == 0 ? a.init_key[x] : 0u;
+    const uint8_t r = find_or_put_lanes<S, B, G, U>(a.t, key, lane == 0, st);
+    if (lane == 0) {
+      a.out->init_status = r;
+      if (r != kNew) sh_go = 0;
+    }
+  }
+  AppendArgs ap;
+  ap.ctr = a.ctr;
+  ap.cap_out = a.f_cap;
+  while (true) {
+    __syncthreads();
+    if (!sh_go) break;
+    const uint64_t n_in = sh_n_in;
+    const uint32_t cur = sh_cur;
+    const uint32_t* fin = a.f[cur];
+    ap.frontier_out = a.f[cur ^ 1u];
+
+    // (1) successors of the level, numbered state by state
+    uint64_t n_succ = 0;
+    for (uint64_t r0 = 0; r0 < n_in; r0 += kSmallThreads) {
+      const uint64_t i = r0 + tid;
+      const bool has = i < n_in;
+      uint32_t sw[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) sw[x] = 0;
+      if (has) load_slot<S>(fin + i * S, sw);
+      const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
+      if (has && c == 0) {
+        const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
+        if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
+      }
+      uint32_t wt = 0;
+      (void)wave_exclusive_scan(c, &wt);
+      if (lane == 0) wave_tot[wave] = wt;
+      __syncthreads();
+      uint64_t wb = n_succ, round = 0;
+      for (uint32_t w = 0; w < kSmallWaves; ++w) {
+        wb += w < wave ? wave_tot[w] : 0u;
+        round += wave_tot[w];
+      }
+      // limit * max_succ <= succ_cap (host bound); refuse rather than overrun
+      if (n_succ + round <= a.succ_cap) {
+        if (wt) emit_window<S, false>(img, sw, has, a.succ + wb * S, 0, wt);
+      } else if (tid == 0) {
+        atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagFrontierOverflow);
+      }
+      n_succ += round;
+      __syncthreads();  // wave_tot is rewritten by the next round
+    }
+    if (n_succ > a.succ_cap) n_succ = 0;
+    if (tid == 0 && n_succ) atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(n_succ));
+    __syncthreads();  // the successors are visible to every wavefront
+
+    // (2) find-or-put of the successors; NEW ones go to the next frontier
+    uint32_t cnt = 0;
+    bool full = false;
+    for (uint64_t k0 = static_cast<uint64_t>(wave) * 64; k0 < n_succ; k0 += kSmallThreads) {
+      const uint64_t idx = k0 + lane;
+      const bool act = idx < n_succ;
+      uint32_t key[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) key[x] = 0;
+      if (act) load_slot<S>(a.succ + idx * S, key);
+      const uint8_t r = find_or_put_lanes<S, B, G, U>(a.t, key, act, st);
+      const bool is_new = act && r == kNew;
+      full |= act && r == kFull;
+      const uint64_t m = __ballot(is_new);
+      if (is_new) store_slot<S>(gbuf + (cnt + __popcll(m & ((1ull << lane) - 1ull))) * S, key);
+      cnt += static_cast<uint32_t>(__popcll(m));
+      if (cnt > kAppendKeys - 64) {
+        wave_lds_sync();
+        append_flush<S>(ap, gbuf, cnt);
+        wave_lds_sync();
+        cnt = 0;
+      }
+    }
+    wave_lds_sync();
+    append_flush<S>(ap, gbuf, cnt);
+    if (__ballot(full) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagTableFull);
+    __syncthreads();  // every append of the level is done
+
+    // (3) the level's size and what comes next
+    if (tid == 0) {
+      auto* tail = ctr_at(a.ctr, kCtrTail);
+      const uint64_t n_next =
+          __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t flags = __hip_atomic_load(ctr_at(a.ctr, kCtrFlags), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t dead = __hip_atomic_load(ctr_at(a.ctr, kCtrDead), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(tail, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (n_next) a.out->levels[sh_levels++] = n_next;
+      sh_n_in = n_next;
+      sh_cur = cur ^ 1u;
+      sh_go = flags == 0 && n_next > 0 && n_next <= a.limit && sh_levels < kSmallLevels &&
+                      n_next <= a.dead_cap - min(dead, a.dead_cap)
+                  ? 1u
+                  : 0u;
+    }
+  }
+  if (tid == 0) {
+    a.out->n_levels = sh_levels;
+    a.out->n_in = sh_n_in;
+    a.out->cur = sh_cur;
+  }
+  flush_stats(a.t, st, nullptr);
+}
+
+template <int S, int B>
+hipError_t launch_small_b(const SmallArgs& a, size_t lds, hipStream_t s) {
+  constexpr int G = B <= 32 ? 4 : 8;
+  constexpr int U = 4;
+  const void* k = reinterpret_cast<const void*>(&small_levels_kernel<S, B, G, U>);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((small_levels_kernel<S, B, G, U>), dim3(1), dim3(kSmallThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+// LDS of a launch: the network image and each wavefront's gather buffer.
+template <int S>
+size_t small_lds(uint32_t img_stride) {
+  return (static_cast<size_t>(img_stride) + kSmallWaves * kAppendKeys * S) * sizeof(uint32_t);
+}
+
+template <int S>
+hipError_t launch_small(uint32_t B, const SmallArgs& a, hipStream_t s) {
+  const size_t lds = small_lds<S>(a.img_stride);
+  switch (B) {
+    case 4: return launch_small_b<S, 4>(a, lds, s);
+    case 8: return launch_small_b<S, 8>(a, lds, s);
+    case 16: return launch_small_b<S, 16>(a, lds, s);
+    case 32: return launch_small_b<S, 32>(a, lds, s);
+    case 64: return launch_small_b<S, 64>(a, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gx

@@ -240,3 +240,34 @@ def test_wide_rule_fan_out(dev, P, k, dedup):
         assert got.n_transitions == want.n_transitions
         assert np.array_equal(got.deadlocks, want.deadlocks)
         assert np.array_equal(t.dump(), want.visited)
+
+
+@pytest.mark.parametrize("n", [1500, 130])
+def test_long_chain_of_small_levels(dev, n):
+    """n levels of one state each: small levels run on one workgroup, up to
+    64 of them per launch, so the chain takes several launches."""
+    got = _explore_and_compare(W.independent_cycles((n,)), B=16, cap=4 * n)
+    assert len(got.levels) == n
+
+
+def test_small_and_large_levels_alternate(dev):
+    """Levels grow past the one-workgroup limit and shrink below it again
+    (the large workload's family at 4 live states: 248,832 states, levels up
+    to about 30,000), in every bucket size."""
+    net = W.large_random_network(live=4)
+    for B in (4, 16, 64):
+        _explore_and_compare(net, B=B, check_dump=(B == 16))
+
+
+@pytest.mark.parametrize("cap,ok", [(1, False), (255, False), (256, True)])
+def test_deadlock_capacity(dev, cap, ok):
+    """wide_rule(4, 4): 256 deadlocks, all in level 1."""
+    net = W.wide_rule(4, 4)
+    with gx.Table(gx.network_words(net), 16, 1024, max_hashes=32) as t:
+        if ok:
+            got = gx.explore(net, t, deadlock_capacity=cap)
+            assert len(got.deadlocks) == 256
+        else:
+            with pytest.raises(gx.GxError) as e:
+                gx.explore(net, t, deadlock_capacity=cap)
+            assert e.value.code == gx.GX_ENOMEM
