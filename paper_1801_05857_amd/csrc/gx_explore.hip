@@ -577,13 +577,12 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
         case 4: e = gx::launch_small<4>(t->B, sa, stream); break;
       }
       if (e != hipSuccess) return GX_EDEVICE;
-      s = read_ctr();
+      if ((s = read_ctr()) != GX_OK) return s;
       if (!init_inserted) {
         init_inserted = true;
         if (small_out->init_status == gx::kFull) return GX_ETABLEFULL;
         if (small_out->init_status != gx::kNew) return GX_EINVAL;
       }
-      if (s != GX_OK) return s;
       for (uint64_t k = 0; k < small_out->n_levels; ++k) levels.push_back(small_out->levels[k]);
       dead_known = ctr(gx::kCtrDead);
       if (dead_known > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;

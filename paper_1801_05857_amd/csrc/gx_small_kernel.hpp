@@ -10,7 +10,7 @@
 
 namespace gx {
 
-constexpr uint32_t kSmallThreads = 1024;  // one workgroup of 16 wavefronts
+constexpr uint32_t kSmallThreads = 512;  // one workgroup of 8 wavefronts
 constexpr uint32_t kSmallWaves = kSmallThreads / 64;
 constexpr uint32_t kSmallLevels = 64;     // levels one launch may complete
 constexpr uint64_t kSmallMaxLevel = 4096; // largest level the workgroup expands
@@ -47,9 +47,8 @@ struct SmallArgs {
 // Every level: (1) the workgroup numbers the level's successors state by
 // state (block prefix sum of the per-state counts) and writes them to the
 // successor buffer with the coalesced lockstep walk of emit_window; (2) all
-// sixteen wavefronts find-or-put those successors, gathering NEW ones per
-// wavefront in LDS and appending them to the next frontier with one atomic
-// add per flush; (3) thread 0 reads the level's size and decides: next level,
+// eight wavefronts find-or-put those successors and append the NEW ones to
+// the next frontier, one atomic add per wavefront and round; (3) thread 0 reads the level's size and decides: next level,
 // done, or back to the host (a level above the limit, a full table, the
 // deadlock buffer short of a level, or kSmallLevels levels done).  Probes use
 // the table's bucket size with (G, U) of this kernel: the claim protocol does
@@ -65,7 +64,6 @@ __global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a
   const uint32_t wave = tid >> 6;
   const int lane = __lane_id();
   uint32_t* img = smem;
-  uint32_t* gbuf = smem + a.img_stride + wave * kAppendKeys * S;
   for (uint32_t k = tid; k < a.img_words; k += kSmallThreads) img[k] = a.img[k];
   if (tid == 0) {
     const uint64_t dead = __hip_atomic_load(ctr_at(a.ctr, kCtrDead), __ATOMIC_RELAXED,
@@ -91,16 +89,13 @@ __global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a
       if (r != kNew) sh_go = 0;
     }
   }
-  AppendArgs ap;
-  ap.ctr = a.ctr;
-  ap.cap_out = a.f_cap;
   while (true) {
     __syncthreads();
     if (!sh_go) break;
     const uint64_t n_in = sh_n_in;
     const uint32_t cur = sh_cur;
     const uint32_t* fin = a.f[cur];
-    ap.frontier_out = a.f[cur ^ 1u];
+    uint32_t* fout = a.f[cur ^ 1u];
 
     // (1) successors of the level, numbered state by state
     uint64_t n_succ = 0;
@@ -138,9 +133,10 @@ __global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a
     if (tid == 0 && n_succ) atomicAdd(ctr_at(a.ctr, kCtrTrans), static_cast<unsigned long long>(n_succ));
     __syncthreads();  // the successors are visible to every wavefront
 
-    // (2) find-or-put of the successors; NEW ones go to the next frontier
-    uint32_t cnt = 0;
-    bool full = false;
+    // (2) find-or-put of the successors; the NEW ones of a round go to the
+    // next frontier with one atomic add per wavefront (levels are small, so
+    // rounds are few)
+    bool full = false, over = false;
     for (uint64_t k0 = static_cast<uint64_t>(wave) * 64; k0 < n_succ; k0 += kSmallThreads) {
       const uint64_t idx = k0 + lane;
       const bool act = idx < n_succ;
@@ -152,18 +148,18 @@ __global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a
       const bool is_new = act && r == kNew;
       full |= act && r == kFull;
       const uint64_t m = __ballot(is_new);
-      if (is_new) store_slot<S>(gbuf + (cnt + __popcll(m & ((1ull << lane) - 1ull))) * S, key);
-      cnt += static_cast<uint32_t>(__popcll(m));
-      if (cnt > kAppendKeys - 64) {
-        wave_lds_sync();
-        append_flush<S>(ap, gbuf, cnt);
-        wave_lds_sync();
-        cnt = 0;
+      if (m) {
+        unsigned long long base = 0;
+        if (lane == 0)
+          base = atomicAdd(ctr_at(a.ctr, kCtrTail), static_cast<unsigned long long>(__popcll(m)));
+        base = __shfl(base, 0, 64);
+        const uint64_t pos = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (is_new && pos < a.f_cap) store_slot<S>(fout + pos * S, key);
+        over |= is_new && pos >= a.f_cap;
       }
     }
-    wave_lds_sync();
-    append_flush<S>(ap, gbuf, cnt);
     if (__ballot(full) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagTableFull);
+    if (__ballot(over) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagFrontierOverflow);
     __syncthreads();  // every append of the level is done
 
     // (3) the level's size and what comes next
@@ -207,15 +203,9 @@ hipError_t launch_small_b(const SmallArgs& a, size_t lds, hipStream_t s) {
   return hipGetLastError();
 }
 
-// LDS of a launch: the network image and each wavefront's gather buffer.
-template <int S>
-size_t small_lds(uint32_t img_stride) {
-  return (static_cast<size_t>(img_stride) + kSmallWaves * kAppendKeys * S) * sizeof(uint32_t);
-}
-
 template <int S>
 hipError_t launch_small(uint32_t B, const SmallArgs& a, hipStream_t s) {
-  const size_t lds = small_lds<S>(a.img_stride);
+  const size_t lds = static_cast<size_t>(a.img_stride) * sizeof(uint32_t);  // the image
   switch (B) {
     case 4: return launch_small_b<S, 4>(a, lds, s);
     case 8: return launch_small_b<S, 8>(a, lds, s);
