@@ -437,7 +437,9 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   if (hipMemcpyAsync(eb.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
                      stream) != hipSuccess ||
       hipMemcpyAsync(eb.f[0], init, state_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(eb.key, init, t->w * sizeof(uint32_t), hipMemcpyHostToDevice, stream) !=
+      // the whole slot (a 3-word state's fourth word is 0): the small-level
+      // kernel reads S words
+      hipMemcpyAsync(eb.key, init, state_bytes, hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
       hipMemsetAsync(eb.ctr, 0, kBlockWords * sizeof(uint64_t), stream) != hipSuccess)
     return GX_EDEVICE;
