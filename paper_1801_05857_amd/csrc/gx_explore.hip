@@ -19,8 +19,11 @@
 //
 // Levels of at most kSmallMaxLevel states (the first levels of every
 // exploration, the last ones of most, all of a small one) are instead
-// expanded by small_levels_kernel on one workgroup, up to kSmallLevels of
-// them per launch with no host round trip in between.
+// expanded on one workgroup, up to kSmallLevels of them per launch with no
+// host round trip in between: the first levels by lds_levels_kernel, which
+// decides NEW or SEEN from an LDS set of the states reached so far (the
+// table holds nothing else yet) and puts them into the table at the end;
+// later small levels by small_levels_kernel, which probes the table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +49,9 @@ extern template hipError_t append_b<4>(uint32_t, uint32_t, uint32_t, const Appen
 extern template hipError_t launch_small<1>(uint32_t, const SmallArgs&, hipStream_t);
 extern template hipError_t launch_small<2>(uint32_t, const SmallArgs&, hipStream_t);
 extern template hipError_t launch_small<4>(uint32_t, const SmallArgs&, hipStream_t);
+extern template hipError_t launch_lds_levels<1>(uint32_t, SmallArgs, size_t, hipStream_t);
+extern template hipError_t launch_lds_levels<2>(uint32_t, SmallArgs, size_t, hipStream_t);
+extern template hipError_t launch_lds_levels<4>(uint32_t, SmallArgs, size_t, hipStream_t);
 }  // namespace gx
 
 namespace gx {
@@ -525,6 +531,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       return GX_EDEVICE;
     if (ctr(gx::kCtrFlags) & gx::kFlagTableFull) return GX_ETABLEFULL;
     if (ctr(gx::kCtrFlags) & gx::kFlagFrontierOverflow) return GX_ENOMEM;
+    if (ctr(gx::kCtrFlags) & gx::kFlagNotEmpty) return GX_EINVAL;
     return GX_OK;
   };
 
@@ -572,11 +579,27 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       sa.out = reinterpret_cast<gx::SmallOut*>(eb.ctr + kCtrWords);
       sa.limit = small_limit;
       sa.init_key = init_inserted ? nullptr : eb.key;
+      sa.set_mask = 0;
+      sa.max_succ = static_cast<uint32_t>(max_succ);
       hipError_t e = hipErrorInvalidValue;
-      switch (S) {
-        case 1: e = gx::launch_small<1>(t->B, sa, stream); break;
-        case 2: e = gx::launch_small<2>(t->B, sa, stream); break;
-        case 4: e = gx::launch_small<4>(t->B, sa, stream); break;
+      bool lds_mode = false;
+      if (!init_inserted) {
+        // the first levels: LDS-resident while the table holds nothing else
+        const size_t lds_limit = gx::lds_per_workgroup(t->device);
+        switch (S) {
+          case 1: e = gx::launch_lds_levels<1>(t->B, sa, lds_limit, stream); break;
+          case 2: e = gx::launch_lds_levels<2>(t->B, sa, lds_limit, stream); break;
+          case 4: e = gx::launch_lds_levels<4>(t->B, sa, lds_limit, stream); break;
+        }
+        lds_mode = e == hipSuccess;
+        if (!lds_mode) (void)hipGetLastError();
+      }
+      if (!lds_mode) {
+        switch (S) {
+          case 1: e = gx::launch_small<1>(t->B, sa, stream); break;
+          case 2: e = gx::launch_small<2>(t->B, sa, stream); break;
+          case 4: e = gx::launch_small<4>(t->B, sa, stream); break;
+        }
       }
       if (e != hipSuccess) return GX_EDEVICE;
       if ((s = read_ctr()) != GX_OK) return s;
@@ -590,7 +613,9 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
       if (dead_known > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;
       n_in = small_out->n_in;
       cur = static_cast<int>(small_out->cur);
-      if (small_out->n_levels == 0 && n_in > 0) return GX_EDEVICE;  // no progress
+      // (an LDS-resident launch may hand its first level straight to the
+      // table-probing kernels)
+      if (!lds_mode && small_out->n_levels == 0 && n_in > 0) return GX_EDEVICE;  // no progress
       continue;
     }
     const int nxt = cur ^ 1;

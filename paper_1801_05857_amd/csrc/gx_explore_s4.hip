@@ -6,4 +6,6 @@ template hipError_t launch_gen<4>(const GenArgs& a, uint32_t grid, size_t lds, h
 template hipError_t append_b<4>(uint32_t B, uint32_t G, uint32_t U, const AppendArgs& a,
                                  uint32_t cus, hipStream_t s);
 template hipError_t launch_small<4>(uint32_t B, const SmallArgs& a, hipStream_t s);
+template hipError_t launch_lds_levels<4>(uint32_t B, SmallArgs a, size_t lds_limit,
+                                         hipStream_t s);
 }  // namespace gx

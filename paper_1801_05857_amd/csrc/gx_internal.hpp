@@ -116,6 +116,9 @@ gx_status sorted_keys(const uint32_t* dev_words, uint64_t total_words, uint32_t 
 gx_status sorted_keys_malloc(const uint32_t* dev_words, uint64_t total_words, uint32_t S,
                              uint32_t w, uint32_t** out);
 
+// LDS bytes one workgroup may use on the device (queried once per device).
+size_t lds_per_workgroup(int device);
+
 // Number of workgroups that keep every CU busy for a grid-stride kernel.
 uint32_t resident_grid(int device, uint32_t per_cu);
 

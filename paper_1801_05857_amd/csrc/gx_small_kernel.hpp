@@ -42,7 +42,14 @@ struct SmallArgs {
   SmallOut* out;
   uint64_t limit;       // largest level this launch expands (limit * max_succ fits)
   const uint32_t* init_key;  // non-null: find-or-put it first (the level-0 state)
+  // LDS-resident levels (lds_levels_kernel) only:
+  uint32_t set_mask;    // entries of the LDS visited set, minus one (a power of two)
+  uint32_t max_succ;    // successors a state can have at most
 };
+
+// A table that held states the launch did not put there (reported as
+// GX_EINVAL: gx_explore needs an empty table).
+constexpr uint32_t kFlagNotEmpty = 16;
 
 // Every level: (1) the workgroup numbers the level's successors state by
 // state (block prefix sum of the per-state counts) and writes them to the
@@ -189,6 +196,200 @@ __global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a
   flush_stats(a.t, st, nullptr);
 }
 
+
+// ------------------------------------------------ LDS-resident first levels
+constexpr uint32_t kLdsChunk = 128;        // staged successors per wavefront chunk
+constexpr uint32_t kLocked = 0xFFFFFFFEu;  // an LDS set entry being written (packed
+                                           // states never hold it: bit 31 is 0)
+
+// Insert-if-absent of key into the workgroup's LDS set (open addressing,
+// linear probing, set_mask + 1 entries of S words); true where this lane put
+// it there.  A multi-word entry is claimed by a compare-and-swap of its first
+// word to kLocked and published by writing the first word last; a lane that
+// meets a locked entry looks at it again in the next step (its owner
+// publishes within the step that claimed it).  Must be reached by the whole
+// wavefront; act false: no key.
+template <int S>
+__device__ inline bool lds_set_insert(uint32_t* set, uint32_t mask, const uint32_t (&key)[S],
+                                      bool act) {
+  bool done = !act, fresh = false;
+  uint32_t h = dedup_hash<S>(key) & mask;
+  while (__ballot(!done)) {
+    if (!done) {
+      uint32_t* e = set + h * S;
+      const uint32_t w0 = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (w0 == kEmpty) {
+        uint32_t expect = kEmpty;
+        if (__hip_atomic_compare_exchange_strong(e, &expect, S == 1 ? key[0] : kLocked,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP)) {
+          if constexpr (S > 1) {
+#pragma unroll
+            for (int x = 1; x < S; ++x)
+              __hip_atomic_store(e + x, key[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __hip_atomic_store(e, key[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          fresh = true;
+          done = true;
+        }
+      } else if (w0 != kLocked) {
+        bool same = w0 == key[0];
+        if constexpr (S > 1) {
+          if (same) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+            for (int x = 1; x < S; ++x)
+              same &= __hip_atomic_load(e + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) ==
+                      key[x];
+          }
+        }
+        if (same)
+          done = true;
+        else
+          h = (h + 1) & mask;
+      }
+    }
+  }
+  return fresh;
+}
+
+// The first levels of an exploration, while the table holds nothing but what
+// this launch puts there: an LDS set of every state reached so far decides
+// NEW or SEEN exactly, with no table probe.  New states are appended to a log
+// in global memory (the successor buffer), level after level, so a level is
+// a contiguous range of the log.  A level is expanded only while the set
+// stays at most three quarters full even if every successor were new.  When
+// the levels end (the exploration is complete, a level would not fit, or
+// kSmallLevels levels are done) every logged state is put into the table --
+// each must come back NEW -- and the current level is copied to frontier
+// buffer 0 for the host.
+template <int S, int B, int G, int U>
+__global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) {
+  extern __shared__ uint32_t smem[];
+  __shared__ uint32_t sh_go, sh_levels, sh_log_n, sh_ls, sh_le;
+  __shared__ unsigned long long sh_trans;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = tid >> 6;
+  const int lane = __lane_id();
+  uint32_t* img = smem;
+  uint32_t* set = smem + a.img_stride;
+  const uint32_t n_set = a.set_mask + 1;
+  uint32_t* stage = set + n_set * S + wave * kLdsChunk * S;
+  uint32_t* log = a.succ;
+  const uint64_t set_cap = static_cast<uint64_t>(n_set) / 4 * 3;
+  for (uint32_t k = tid; k < a.img_words; k += kSmallThreads) img[k] = a.img[k];
+  for (uint32_t k = tid; k < n_set * S; k += kSmallThreads) set[k] = kEmpty;
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t key[S];
+#pragma unroll
+    for (int x = 0; x < S; ++x) key[x] = a.init_key[x];
+    (void)lds_set_insert<S>(set, a.set_mask, key, lane == 0);
+    if (lane == 0) {
+      store_slot<S>(log, key);
+      sh_log_n = 1;
+      sh_ls = 0;
+      sh_le = 1;
+      sh_levels = 0;
+      sh_trans = 0;
+      sh_go = a.limit >= 1 && 1 + static_cast<uint64_t>(a.max_succ) <= min(set_cap, a.succ_cap)
+                  ? 1u
+                  : 0u;
+    }
+  }
+  while (true) {
+    __syncthreads();
+    if (!sh_go) break;
+    const uint32_t ls = sh_ls, n_in = sh_le - sh_ls;
+    for (uint32_t g0 = wave * 64; g0 < n_in; g0 += kSmallThreads) {
+      const uint32_t i = g0 + lane;
+      const bool has = i < n_in;
+      uint32_t sw[S];
+#pragma unroll
+      for (int x = 0; x < S; ++x) sw[x] = 0;
+      if (has) load_slot<S>(log + static_cast<uint64_t>(ls + i) * S, sw);
+      const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
+      if (has && c == 0) {
+        const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
+        if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
+      }
+      uint32_t total = 0;
+      (void)wave_exclusive_scan(c, &total);
+      if (lane == 0 && total) atomicAdd(&sh_trans, static_cast<unsigned long long>(total));
+      for (uint32_t lo = 0; lo < total; lo += kLdsChunk) {
+        const uint32_t hi = min(total, lo + kLdsChunk);
+        emit_window<S, true>(img, sw, has, stage, lo, hi);
+        wave_lds_sync();
+        for (uint32_t r0 = 0; r0 < hi - lo; r0 += 64) {
+          const uint32_t idx = r0 + lane;
+          const bool act = idx < hi - lo;
+          uint32_t key[S];
+#pragma unroll
+          for (int x = 0; x < S; ++x) key[x] = act ? stage[idx * S + x] : 0u;
+          const bool fresh = lds_set_insert<S>(set, a.set_mask, key, act);
+          const uint64_t m = __ballot(fresh);
+          if (m) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&sh_log_n, static_cast<uint32_t>(__popcll(m)));
+            base = __shfl(base, 0, 64);
+            if (fresh)
+              store_slot<S>(log + (base + __popcll(m & ((1ull << lane) - 1ull))) * S, key);
+          }
+        }
+        wave_lds_sync();  // the stage is rewritten by the next chunk
+      }
+    }
+    __syncthreads();  // the level's new states are logged
+    if (tid == 0) {
+      const uint32_t le = sh_le, log_n = sh_log_n, n_next = log_n - le;
+      const uint64_t dead = __hip_atomic_load(ctr_at(a.ctr, kCtrDead), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+      if (n_next) a.out->levels[sh_levels++] = n_next;
+      sh_ls = le;
+      sh_le = log_n;
+      const uint64_t worst = log_n + static_cast<uint64_t>(n_next) * a.max_succ;
+      // (n_next <= limit: the level after it fits the frontier buffer, which
+      // receives the current level when the launch ends)
+      sh_go = n_next > 0 && n_next <= a.limit && sh_levels < kSmallLevels &&
+                      worst <= min(set_cap, a.succ_cap) &&
+                      n_next <= a.dead_cap - min(dead, a.dead_cap)
+                  ? 1u
+                  : 0u;
+    }
+  }
+  __syncthreads();
+  // every logged state into the table; the table held none of them
+  LaneStats st;
+  const uint32_t log_n = sh_log_n;
+  bool full = false, seen = false;
+  for (uint32_t k0 = wave * 64; k0 < log_n; k0 += kSmallThreads) {
+    const uint32_t idx = k0 + lane;
+    const bool act = idx < log_n;
+    uint32_t key[S];
+#pragma unroll
+    for (int x = 0; x < S; ++x) key[x] = 0;
+    if (act) load_slot<S>(log + static_cast<uint64_t>(idx) * S, key);
+    const uint8_t r = find_or_put_lanes<S, B, G, U>(a.t, key, act, st);
+    full |= act && r == kFull;
+    seen |= act && r != kNew && r != kFull;
+    if (idx == 0) a.out->init_status = r;
+  }
+  if (__ballot(full) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagTableFull);
+  if (__ballot(seen) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagNotEmpty);
+  // the current level becomes frontier buffer 0 (when the levels go on)
+  const uint32_t ls = sh_ls, n_cur = sh_le - sh_ls;
+  for (uint32_t k = tid; k < n_cur * S; k += kSmallThreads)
+    a.f[0][k] = log[static_cast<uint64_t>(ls) * S + k];
+  if (tid == 0) {
+    a.out->n_levels = sh_levels;
+    a.out->n_in = n_cur;  // 0: the last level expanded found nothing new
+    a.out->cur = 0;
+    if (sh_trans) atomicAdd(ctr_at(a.ctr, kCtrTrans), sh_trans);
+  }
+  flush_stats(a.t, st, nullptr);
+}
+
 template <int S, int B>
 hipError_t launch_small_b(const SmallArgs& a, size_t lds, hipStream_t s) {
   constexpr int G = B <= 32 ? 4 : 8;
@@ -201,6 +402,47 @@ hipError_t launch_small_b(const SmallArgs& a, size_t lds, hipStream_t s) {
   }
   hipLaunchKernelGGL((small_levels_kernel<S, B, G, U>), dim3(1), dim3(kSmallThreads), lds, s, a);
   return hipGetLastError();
+}
+
+// LDS bytes of an LDS-resident launch with 2^set_bits set entries.
+template <int S>
+size_t lds_levels_bytes(uint32_t img_stride, uint32_t set_bits) {
+  return (static_cast<size_t>(img_stride) + (size_t(S) << set_bits) +
+          kSmallWaves * kLdsChunk * S) * sizeof(uint32_t);
+}
+
+template <int S, int B>
+hipError_t launch_lds_b(const SmallArgs& a, size_t lds, hipStream_t s) {
+  constexpr int G = B <= 32 ? 4 : 8;
+  constexpr int U = 4;
+  const void* k = reinterpret_cast<const void*>(&lds_levels_kernel<S, B, G, U>);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((lds_levels_kernel<S, B, G, U>), dim3(1), dim3(kSmallThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+// Launch the LDS-resident first levels with the largest visited set that fits
+// lds_limit bytes of LDS; returns hipErrorInvalidValue (nothing launched)
+// when not even 2^10 entries fit.
+template <int S>
+hipError_t launch_lds_levels(uint32_t B, SmallArgs a, size_t lds_limit, hipStream_t s) {
+  uint32_t bits = 20;
+  while (bits >= 10 && lds_levels_bytes<S>(a.img_stride, bits) > lds_limit) --bits;
+  if (bits < 10) return hipErrorInvalidValue;
+  a.set_mask = (1u << bits) - 1u;
+  const size_t lds = lds_levels_bytes<S>(a.img_stride, bits);
+  switch (B) {
+    case 4: return launch_lds_b<S, 4>(a, lds, s);
+    case 8: return launch_lds_b<S, 8>(a, lds, s);
+    case 16: return launch_lds_b<S, 16>(a, lds, s);
+    case 32: return launch_lds_b<S, 32>(a, lds, s);
+    case 64: return launch_lds_b<S, 64>(a, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int S>

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <mutex>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -187,6 +189,25 @@ gx_status sorted_keys(const uint32_t* dev_words, uint64_t total_words, uint32_t 
   }
   *n_out = count;
   return GX_OK;
+}
+
+size_t lds_per_workgroup(int device) {
+  static std::atomic<int64_t> cached[64];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (auto& c : cached) c.store(-1);
+  });
+  if (device < 0 || device >= 64) return 65536;
+  int64_t v = cached[device].load();
+  if (v < 0) {
+    int optin = 0, plain = 0;
+    (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device);
+    (void)hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    (void)hipGetLastError();
+    v = std::max<int64_t>(std::max(optin, plain), 32768) - 1024;  // room for static LDS
+    cached[device].store(v);
+  }
+  return static_cast<size_t>(v);
 }
 
 gx_status sorted_keys_malloc(const uint32_t* dev_words, uint64_t total_words, uint32_t S,
