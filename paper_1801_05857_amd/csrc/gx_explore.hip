@@ -400,21 +400,22 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   // resident buffers of the table (allocated on first use, grow-only)
   const uint32_t img_words = static_cast<uint32_t>(ni.img.size());
   const uint32_t img_stride = (img_words + 3) & ~3u;
-  if (eb.img_cap < img_stride) {
-    if (gx::grow(reinterpret_cast<void**>(&eb.img), &eb.img_cap, img_stride, sizeof(uint32_t), 0,
-                 stream, img_stride) != hipSuccess)
-      return GX_ENOMEM;
-  }
-  // the level's counters, then what a small-level launch reports
+  // the control block: the level's counters, what a small-level launch
+  // reports (read back together), the initial state's slot, the image
   constexpr size_t kCtrWords = gx::kCtrCount * gx::kCtrSpread;
   constexpr size_t kBlockWords = kCtrWords + sizeof(gx::SmallOut) / sizeof(uint64_t);
-  if (!eb.ctr && (hipMalloc(&eb.ctr, kBlockWords * sizeof(uint64_t)) != hipSuccess ||
-                  hipHostMalloc(&eb.ctr_host, kBlockWords * sizeof(uint64_t)) != hipSuccess ||
-                  hipMalloc(&eb.status, 8) != hipSuccess ||
-                  hipMalloc(&eb.key, 4 * sizeof(uint32_t)) != hipSuccess)) {
+  constexpr size_t kControlBytes =
+      kBlockWords * sizeof(uint64_t) + 4 * sizeof(uint32_t) + gx::kImgMaxWords * sizeof(uint32_t);
+  if (img_stride > gx::kImgMaxWords) return GX_EINVAL;
+  if (!eb.ctr && (hipMalloc(&eb.ctr, kControlBytes) != hipSuccess ||
+                  hipHostMalloc(&eb.ctr_host, kControlBytes) != hipSuccess ||
+                  hipMalloc(&eb.status, 8) != hipSuccess)) {
     (void)hipGetLastError();
     return GX_ENOMEM;
   }
+  eb.key = reinterpret_cast<uint32_t*>(eb.ctr + kBlockWords);
+  eb.img = eb.key + 4;
+  eb.img_cap = gx::kImgMaxWords;
   for (int k = 0; k < 2; ++k)
     if ((s = grow_buf(&eb.f[k], &eb.f_cap[k], 1, 0, max_cap)) != GX_OK) return s;
   if ((s = grow_buf(&eb.dead, &eb.dead_cap, 1, 0, max_dead)) != GX_OK) return s;
@@ -437,17 +438,23 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   // the level's counters, spread over cache lines on the device, read back
   // into pinned host memory
   uint64_t* ctr_raw = eb.ctr_host;
-  std::memset(ctr_raw, 0, kBlockWords * sizeof(uint64_t));
   const gx::SmallOut* small_out = reinterpret_cast<const gx::SmallOut*>(ctr_raw + kCtrWords);
   auto ctr = [&](uint32_t k) { return ctr_raw[k * gx::kCtrSpread]; };
-  if (hipMemcpyAsync(eb.img, ni.img.data(), img_words * sizeof(uint32_t), hipMemcpyHostToDevice,
-                     stream) != hipSuccess ||
-      hipMemcpyAsync(eb.f[0], init, state_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      // the whole slot (a 3-word state's fourth word is 0): the small-level
-      // kernel reads S words
-      hipMemcpyAsync(eb.key, init, state_bytes, hipMemcpyHostToDevice, stream) !=
-          hipSuccess ||
-      hipMemsetAsync(eb.ctr, 0, kBlockWords * sizeof(uint64_t), stream) != hipSuccess)
+  {
+    // zeroed counters, the initial state's whole slot (a 3-word state's
+    // fourth word is 0) and the image, up in one copy from pinned memory
+    std::memset(ctr_raw, 0, kBlockWords * sizeof(uint64_t));
+    uint32_t* hkey = reinterpret_cast<uint32_t*>(ctr_raw + kBlockWords);
+    std::memcpy(hkey, init, 4 * sizeof(uint32_t));
+    std::memcpy(hkey + 4, ni.img.data(), img_words * sizeof(uint32_t));
+    const size_t up = kBlockWords * sizeof(uint64_t) + (4 + img_words) * sizeof(uint32_t);
+    if (hipMemcpyAsync(eb.ctr, ctr_raw, up, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return GX_EDEVICE;
+  }
+  // the first level for the table-probing kernels (the small-level kernels
+  // take the initial state from eb.key)
+  if (small_limit == 0 &&
+      hipMemcpyAsync(eb.f[0], eb.key, state_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return GX_EDEVICE;
   // the initial state must be new, i.e. the table must not hold it yet (with
   // small levels, the first small launch inserts it)

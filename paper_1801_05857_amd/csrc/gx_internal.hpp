@@ -12,7 +12,7 @@
 // Device buffers of the exploration driver, owned by a table and reused by
 // every exploration into it (grow-only).
 struct gx_explore_buffers {
-  uint32_t* img = nullptr;  // network image
+  uint32_t* img = nullptr;  // network image (in the control block, see ctr)
   uint64_t img_cap = 0;     // words
   uint32_t* f[2] = {nullptr, nullptr};
   uint64_t f_cap[2] = {0, 0};  // states
@@ -20,10 +20,14 @@ struct gx_explore_buffers {
   uint64_t dead_cap = 0;  // states
   uint32_t* succ = nullptr;  // successors of a level slice, before the table probe
   uint64_t succ_cap = 0;     // states
-  uint64_t* ctr = nullptr;  // level counters, one cache line each
-  uint64_t* ctr_host = nullptr;  // pinned host copy of ctr (per-level read-back)
+  // control block (device) and its pinned host mirror: the level counters
+  // (one cache line each) and what a small-level launch reports, then the
+  // initial state's slot and the network image; one copy up per exploration,
+  // the counters' part read back after every level
+  uint64_t* ctr = nullptr;
+  uint64_t* ctr_host = nullptr;
   uint8_t* status = nullptr;
-  uint32_t* key = nullptr;  // 4 words
+  uint32_t* key = nullptr;  // the initial state, 4 words (in the control block)
   // safety monitor: bad-state bitmask, violating states, their running count
   uint32_t* mon = nullptr;
   uint64_t mon_cap = 0;      // words

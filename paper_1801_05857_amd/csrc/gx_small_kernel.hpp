@@ -4,6 +4,7 @@
 // instances to small search layers and per-layer overhead).
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 
 #include "gx_explore_kernel.hpp"
@@ -21,7 +22,8 @@ struct SmallOut {
   uint64_t n_in;         // size of the current level (0: the exploration is over)
   uint64_t cur;          // the frontier buffer holding it
   uint64_t init_status;  // find-or-put status of the initial state (when inserted)
-  uint64_t pad[4];
+  uint64_t log_n;        // LDS-resident launch: states it logged (they go into the table)
+  uint64_t pad[3];
   uint64_t levels[kSmallLevels];
 };
 
@@ -198,7 +200,10 @@ __global__ __launch_bounds__(kSmallThreads) void small_levels_kernel(SmallArgs a
 
 
 // ------------------------------------------------ LDS-resident first levels
-constexpr uint32_t kLdsChunk = 128;        // staged successors per wavefront chunk
+template <int S>
+constexpr uint32_t lds_chunk() {  // staged successors per wavefront chunk (2 KiB)
+  return 512u / S;
+}
 constexpr uint32_t kLocked = 0xFFFFFFFEu;  // an LDS set entry being written (packed
                                            // states never hold it: bit 31 is 0)
 
@@ -261,21 +266,22 @@ __device__ inline bool lds_set_insert(uint32_t* set, uint32_t mask, const uint32
 // a contiguous range of the log.  A level is expanded only while the set
 // stays at most three quarters full even if every successor were new.  When
 // the levels end (the exploration is complete, a level would not fit, or
-// kSmallLevels levels are done) every logged state is put into the table --
-// each must come back NEW -- and the current level is copied to frontier
-// buffer 0 for the host.
+// kSmallLevels levels are done) the current level is copied to frontier
+// buffer 0 for the host, and log_insert_kernel puts every logged state into
+// the table.
 template <int S, int B, int G, int U>
 __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) {
   extern __shared__ uint32_t smem[];
-  __shared__ uint32_t sh_go, sh_levels, sh_log_n, sh_ls, sh_le;
-  __shared__ unsigned long long sh_trans;
+  constexpr uint32_t kChunk = lds_chunk<S>();
+  __shared__ uint32_t sh_go, sh_levels, sh_log_n, sh_ls, sh_le, sh_dead;
+  __shared__ unsigned long long sh_trans, sh_dead0;
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = tid >> 6;
   const int lane = __lane_id();
   uint32_t* img = smem;
   uint32_t* set = smem + a.img_stride;
   const uint32_t n_set = a.set_mask + 1;
-  uint32_t* stage = set + n_set * S + wave * kLdsChunk * S;
+  uint32_t* stage = set + n_set * S + wave * kChunk * S;
   uint32_t* log = a.succ;
   const uint64_t set_cap = static_cast<uint64_t>(n_set) / 4 * 3;
   for (uint32_t k = tid; k < a.img_words; k += kSmallThreads) img[k] = a.img[k];
@@ -293,6 +299,9 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
       sh_le = 1;
       sh_levels = 0;
       sh_trans = 0;
+      sh_dead = 0;
+      sh_dead0 = __hip_atomic_load(ctr_at(a.ctr, kCtrDead), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
       sh_go = a.limit >= 1 && 1 + static_cast<uint64_t>(a.max_succ) <= min(set_cap, a.succ_cap)
                   ? 1u
                   : 0u;
@@ -313,12 +322,13 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
       if (has && c == 0) {
         const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
         if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
+        atomicAdd(&sh_dead, 1u);
       }
       uint32_t total = 0;
       (void)wave_exclusive_scan(c, &total);
       if (lane == 0 && total) atomicAdd(&sh_trans, static_cast<unsigned long long>(total));
-      for (uint32_t lo = 0; lo < total; lo += kLdsChunk) {
-        const uint32_t hi = min(total, lo + kLdsChunk);
+      for (uint32_t lo = 0; lo < total; lo += kChunk) {
+        const uint32_t hi = min(total, lo + kChunk);
         emit_window<S, true>(img, sw, has, stage, lo, hi);
         wave_lds_sync();
         for (uint32_t r0 = 0; r0 < hi - lo; r0 += 64) {
@@ -343,8 +353,7 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
     __syncthreads();  // the level's new states are logged
     if (tid == 0) {
       const uint32_t le = sh_le, log_n = sh_log_n, n_next = log_n - le;
-      const uint64_t dead = __hip_atomic_load(ctr_at(a.ctr, kCtrDead), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t dead = sh_dead0 + sh_dead;
       if (n_next) a.out->levels[sh_levels++] = n_next;
       sh_ls = le;
       sh_le = log_n;
@@ -359,24 +368,6 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
     }
   }
   __syncthreads();
-  // every logged state into the table; the table held none of them
-  LaneStats st;
-  const uint32_t log_n = sh_log_n;
-  bool full = false, seen = false;
-  for (uint32_t k0 = wave * 64; k0 < log_n; k0 += kSmallThreads) {
-    const uint32_t idx = k0 + lane;
-    const bool act = idx < log_n;
-    uint32_t key[S];
-#pragma unroll
-    for (int x = 0; x < S; ++x) key[x] = 0;
-    if (act) load_slot<S>(log + static_cast<uint64_t>(idx) * S, key);
-    const uint8_t r = find_or_put_lanes<S, B, G, U>(a.t, key, act, st);
-    full |= act && r == kFull;
-    seen |= act && r != kNew && r != kFull;
-    if (idx == 0) a.out->init_status = r;
-  }
-  if (__ballot(full) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagTableFull);
-  if (__ballot(seen) && lane == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagNotEmpty);
   // the current level becomes frontier buffer 0 (when the levels go on)
   const uint32_t ls = sh_ls, n_cur = sh_le - sh_ls;
   for (uint32_t k = tid; k < n_cur * S; k += kSmallThreads)
@@ -385,9 +376,41 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
     a.out->n_levels = sh_levels;
     a.out->n_in = n_cur;  // 0: the last level expanded found nothing new
     a.out->cur = 0;
+    a.out->log_n = sh_log_n;
     if (sh_trans) atomicAdd(ctr_at(a.ctr, kCtrTrans), sh_trans);
   }
-  flush_stats(a.t, st, nullptr);
+}
+
+// The states an LDS-resident launch logged go into the table, spread over
+// the device (launched right after it on the same stream).  They are
+// distinct and the table held none of them (it was empty when the
+// exploration started), so each must come back NEW: FULL raises the
+// table-full flag, anything else kFlagNotEmpty.  The initial state (log
+// entry 0) reports its status in out->init_status.
+template <int S, int B, int G, int U>
+__global__ __launch_bounds__(256) void log_insert_kernel(TableDev t, const uint32_t* log,
+                                                         SmallOut* out, uint64_t* ctr) {
+  const uint64_t n = out->log_n;
+  const int lane = __lane_id();
+  const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+  LaneStats st;
+  bool full = false, seen = false;
+  for (uint64_t base = wave * 64; base < n; base += n_waves * 64) {
+    const uint64_t idx = base + lane;
+    const bool act = idx < n;
+    uint32_t key[S];
+#pragma unroll
+    for (int x = 0; x < S; ++x) key[x] = 0;
+    if (act) load_slot<S>(log + idx * S, key);
+    const uint8_t r = find_or_put_lanes<S, B, G, U>(t, key, act, st);
+    full |= act && r == kFull;
+    seen |= act && r != kNew && r != kFull;
+    if (idx == 0) out->init_status = r;
+  }
+  if (__ballot(full) && lane == 0) atomicOr(ctr_at(ctr, kCtrFlags), kFlagTableFull);
+  if (__ballot(seen) && lane == 0) atomicOr(ctr_at(ctr, kCtrFlags), kFlagNotEmpty);
+  flush_stats(t, st, nullptr);
 }
 
 template <int S, int B>
@@ -408,7 +431,7 @@ hipError_t launch_small_b(const SmallArgs& a, size_t lds, hipStream_t s) {
 template <int S>
 size_t lds_levels_bytes(uint32_t img_stride, uint32_t set_bits) {
   return (static_cast<size_t>(img_stride) + (size_t(S) << set_bits) +
-          kSmallWaves * kLdsChunk * S) * sizeof(uint32_t);
+          kSmallWaves * lds_chunk<S>() * S) * sizeof(uint32_t);
 }
 
 template <int S, int B>
@@ -422,12 +445,20 @@ hipError_t launch_lds_b(const SmallArgs& a, size_t lds, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((lds_levels_kernel<S, B, G, U>), dim3(1), dim3(kSmallThreads), lds, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the logged states (at most three quarters of the set) into the table
+  const uint32_t grid = static_cast<uint32_t>(
+      std::min<uint64_t>(256, (static_cast<uint64_t>(a.set_mask) + 1) / 256 + 1));
+  hipLaunchKernelGGL((log_insert_kernel<S, B, G, U>), dim3(grid), dim3(256), 0, s, a.t, a.succ,
+                     a.out, a.ctr);
   return hipGetLastError();
 }
 
 // Launch the LDS-resident first levels with the largest visited set that fits
-// lds_limit bytes of LDS; returns hipErrorInvalidValue (nothing launched)
-// when not even 2^10 entries fit.
+// lds_limit bytes of LDS, then the insertion of the states they logged;
+// returns hipErrorInvalidValue (nothing launched) when not even 2^10 entries
+// fit.
 template <int S>
 hipError_t launch_lds_levels(uint32_t B, SmallArgs a, size_t lds_limit, hipStream_t s) {
   uint32_t bits = 20;

@@ -121,11 +121,12 @@ void free_table(gx_table* t) {
   if (t->hc) (void)hipFree(t->hc);
   if (t->counters) (void)hipFree(t->counters);
   gx_explore_buffers& e = t->eb;
-  for (void* p : {static_cast<void*>(e.img), static_cast<void*>(e.f[0]),
-                  static_cast<void*>(e.f[1]), static_cast<void*>(e.dead), static_cast<void*>(e.succ),
+  // (e.key and e.img live in e.ctr's allocation, the control block)
+  for (void* p : {static_cast<void*>(e.f[0]), static_cast<void*>(e.f[1]),
+                  static_cast<void*>(e.dead), static_cast<void*>(e.succ),
                   static_cast<void*>(e.ctr), static_cast<void*>(e.status),
-                  static_cast<void*>(e.key), static_cast<void*>(e.mon),
-                  static_cast<void*>(e.viol), static_cast<void*>(e.viol_ctr)})
+                  static_cast<void*>(e.mon), static_cast<void*>(e.viol),
+                  static_cast<void*>(e.viol_ctr)})
     if (p) (void)hipFree(p);
   if (e.ctr_host) (void)hipHostFree(e.ctr_host);
   delete t;
