@@ -775,6 +775,7 @@ def main():
             t.close()
         return
 
+    t_bench = time.perf_counter()
     n = 1 << args.log2n
     n_distinct = n // 2
     keys, _ = W.duplicated_stream_torch(n_distinct, 2, SEED, dev)
@@ -869,23 +870,35 @@ def main():
             "Mops_per_s_kernel": round(n / (r9["fop_ms"] * 1e-3) / 1e6, 1),
             "probes_per_op": round(r9["probes_per_op"], 4), "max_hash_index": r9["max_hash_index"],
             "full": r9["full"], "max_hashes": 128, "table_slots": r9["n_slots"]}
+    def progress(leg):
+        print(json.dumps({"bench_leg_done": leg, "elapsed_s": round(time.perf_counter() - t_bench, 1)}),
+              file=sys.stderr, flush=True)
+
+    progress("find-or-put")
     out["tiny"] = run_tiny(gx, torch, W)
+    progress("tiny")
     del keys
     torch.cuda.empty_cache()
     if not args.no_explore:
         out["explore"] = run_explore_leg(gx, torch, W)
+        progress("explore")
     if not args.no_batch:
         out.update(run_batch(gx, torch, W, args.batch_n, B=args.batch_bucket,
                              G=args.batch_subgroup, U=args.batch_kps))
+        progress("batched")
     if not args.no_serve:
         out["served"] = run_serve(gx, torch, W, args.serve_n)
+        progress("served")
     if not args.no_dup:
         out["duplication_sweep"] = dup_sweep_summary(run_dup_sweep(gx, torch, W))
+        progress("duplication sweep")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        progress("cpu baseline")
         if not args.no_explore:
             out["cpu_baseline"]["explore"] = cpu_explore_baseline(W)
             out["cpu_baseline"]["explore_all_cores"] = cpu_explore_all_cores(W)
+            progress("cpu explore baselines")
         if not args.no_batch:
             out["cpu_baseline"]["batched_all_cores"] = cpu_batch_all_cores(W)
     print(json.dumps(out), flush=True)
