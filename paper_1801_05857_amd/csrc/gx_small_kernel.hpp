@@ -204,10 +204,6 @@ template <int S>
 constexpr uint32_t lds_chunk() {  // staged successors per wavefront chunk (2 KiB)
   return 512u / S;
 }
-template <int S>
-constexpr uint32_t lds_level() {  // states of a level kept in LDS (8 KiB)
-  return 2048u / S;
-}
 constexpr uint32_t kLocked = 0xFFFFFFFEu;  // an LDS set entry being written (packed
                                            // states never hold it: bit 31 is 0)
 
@@ -277,7 +273,7 @@ template <int S, int B, int G, int U>
 __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) {
   extern __shared__ uint32_t smem[];
   constexpr uint32_t kChunk = lds_chunk<S>();
-  __shared__ uint32_t sh_go, sh_levels, sh_log_n, sh_ls, sh_le, sh_dead, sh_par;
+  __shared__ uint32_t sh_go, sh_levels, sh_log_n, sh_ls, sh_le, sh_dead;
   __shared__ unsigned long long sh_trans, sh_dead0;
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = tid >> 6;
@@ -285,9 +281,7 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
   uint32_t* img = smem;
   uint32_t* set = smem + a.img_stride;
   const uint32_t n_set = a.set_mask + 1;
-  constexpr uint32_t kLevel = lds_level<S>();
-  uint32_t* fr = set + n_set * S;  // two levels of up to kLevel states
-  uint32_t* stage = fr + 2 * kLevel * S + wave * kChunk * S;
+  uint32_t* stage = set + n_set * S + wave * kChunk * S;
   uint32_t* log = a.succ;
   const uint64_t set_cap = static_cast<uint64_t>(n_set) / 4 * 3;
   for (uint32_t k = tid; k < a.img_words; k += kSmallThreads) img[k] = a.img[k];
@@ -300,8 +294,6 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
     (void)lds_set_insert<S>(set, a.set_mask, key, lane == 0);
     if (lane == 0) {
       store_slot<S>(log, key);
-      store_slot<S>(fr, key);
-      sh_par = 0;
       sh_log_n = 1;
       sh_ls = 0;
       sh_le = 1;
@@ -318,18 +310,14 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
   while (true) {
     __syncthreads();
     if (!sh_go) break;
-    const uint32_t ls = sh_ls, n_in = sh_le - sh_ls, le = sh_le;
-    // the level's states: from LDS when they all fit there, else from the log
-    const uint32_t* cur_fr = fr + sh_par * kLevel * S;
-    uint32_t* nxt_fr = fr + (sh_par ^ 1u) * kLevel * S;
-    const bool in_lds = n_in <= kLevel;
+    const uint32_t ls = sh_ls, n_in = sh_le - sh_ls;
     for (uint32_t g0 = wave * 64; g0 < n_in; g0 += kSmallThreads) {
       const uint32_t i = g0 + lane;
       const bool has = i < n_in;
       uint32_t sw[S];
 #pragma unroll
       for (int x = 0; x < S; ++x) sw[x] = 0;
-      if (has) load_slot<S>(in_lds ? cur_fr + i * S : log + static_cast<uint64_t>(ls + i) * S, sw);
+      if (has) load_slot<S>(log + static_cast<uint64_t>(ls + i) * S, sw);
       const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
       if (has && c == 0) {
         const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
@@ -355,11 +343,8 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(&sh_log_n, static_cast<uint32_t>(__popcll(m)));
             base = __shfl(base, 0, 64);
-            const uint32_t pos = base + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
-            if (fresh) {
-              store_slot<S>(log + static_cast<uint64_t>(pos) * S, key);
-              if (pos - le < kLevel) store_slot<S>(nxt_fr + (pos - le) * S, key);
-            }
+            if (fresh)
+              store_slot<S>(log + (base + __popcll(m & ((1ull << lane) - 1ull))) * S, key);
           }
         }
         wave_lds_sync();  // the stage is rewritten by the next chunk
@@ -370,7 +355,6 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
       const uint32_t le = sh_le, log_n = sh_log_n, n_next = log_n - le;
       const uint64_t dead = sh_dead0 + sh_dead;
       if (n_next) a.out->levels[sh_levels++] = n_next;
-      sh_par ^= 1u;
       sh_ls = le;
       sh_le = log_n;
       const uint64_t worst = log_n + static_cast<uint64_t>(n_next) * a.max_succ;
@@ -446,7 +430,7 @@ hipError_t launch_small_b(const SmallArgs& a, size_t lds, hipStream_t s) {
 // LDS bytes of an LDS-resident launch with 2^set_bits set entries.
 template <int S>
 size_t lds_levels_bytes(uint32_t img_stride, uint32_t set_bits) {
-  return (static_cast<size_t>(img_stride) + (size_t(S) << set_bits) + 2 * lds_level<S>() * S +
+  return (static_cast<size_t>(img_stride) + (size_t(S) << set_bits) +
           kSmallWaves * lds_chunk<S>() * S) * sizeof(uint32_t);
 }
 
