@@ -430,7 +430,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     const uint64_t room = std::min<uint64_t>(
         std::min<uint64_t>(eb.f_cap[0], eb.f_cap[1]),
         std::min<uint64_t>(eb.succ_cap, max_cap));
-    small_limit = std::min<uint64_t>(gx::kSmallMaxLevel, room / max_succ);
+    small_limit = std::min<uint64_t>(
+        gx::kSmallMaxLevel, std::min<uint64_t>(room, gx::kSmallSuccBudget) / max_succ);
   }
 
   uint32_t init[4] = {0, 0, 0, 0};

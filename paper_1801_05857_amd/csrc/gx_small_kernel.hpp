@@ -15,6 +15,7 @@ constexpr uint32_t kSmallThreads = 512;  // one workgroup of 8 wavefronts
 constexpr uint32_t kSmallWaves = kSmallThreads / 64;
 constexpr uint32_t kSmallLevels = 64;     // levels one launch may complete
 constexpr uint64_t kSmallMaxLevel = 4096; // largest level the workgroup expands
+constexpr uint64_t kSmallSuccBudget = 4096;  // and at most this many successors (worst case)
 
 // What a launch leaves for the host (read back with the level counters).
 struct SmallOut {
