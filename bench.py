@@ -79,6 +79,8 @@ def parse():
                     help="explore Token Ring instances of 2..16 nodes")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter scale reference)")
+    ap.add_argument("--fop-only", action="store_true",
+                    help="only the timed find-or-put steps (for profiling)")
     return ap.parse_args()
 
 
@@ -686,6 +688,16 @@ def main():
     gx.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calib_copy:
+        # one plain device copy of 1 GiB: the reference that scales the HBM
+        # byte counters of a profiled run
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(3)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
 
     if args.probe:
         for gib in args.probe_gib or [2]:
@@ -781,13 +793,6 @@ def main():
     keys, _ = W.duplicated_stream_torch(n_distinct, 2, SEED, dev)
     torch.cuda.synchronize()
 
-    if args.calib_copy:
-        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(3)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     if args.sweep:
         for alpha, H in ((0.5, 8), (0.9, 128)):
@@ -850,6 +855,9 @@ def main():
         "find_or_put_Mops_per_s_kernel": round(n / (r["fop_ms"] * 1e-3) / 1e6, 1),
         "clear_ms": round(r["clear_ms"], 4),
     }
+    if args.fop_only:
+        print(json.dumps(out), flush=True)
+        return
     # the achievable random-read rate at the bucket's size, the second
     # denominator of the roofline
     ceil = random_read_ceiling(gx, torch, max(4 * args.bucket, GRANULE))
