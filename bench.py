@@ -187,6 +187,27 @@ def measured_traffic(args):
     return float(meta["traffic_bytes_per_launch"])
 
 
+def measured_explore_traffic():
+    """HBM bytes per exploration of the large workload from the committed
+    rocprofv3 counter summary, when it was taken on the same kernel and
+    driver sources and table configuration (otherwise None)."""
+    import hashlib
+
+    import workloads as W
+
+    path = os.path.join(ROOT, "profiles", "explore_large_random_12x64_B16_G4_traffic.json")
+    try:
+        meta = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    csrc = os.path.join(ROOT, "paper_1801_05857_amd", "csrc")
+    src = "".join(open(os.path.join(csrc, f)).read() for f in meta["source_files"])
+    cfg = dict(W.LARGE_EXPLORE, table_slots=W.LARGE_TABLE_SLOTS)
+    if meta.get("source_sha256") != hashlib.sha256(src.encode()).hexdigest() or meta.get("config") != cfg:
+        return None
+    return float(meta["traffic_bytes_per_exploration"])
+
+
 def cpu_baseline(target_s: float = 15.0):
     """The oracle (std::unordered_set insertion, one thread) on a bounded
     sample of the same workload shape: a stream of 2^k distinct two-word keys
@@ -386,6 +407,12 @@ def run_explore_leg(gx, torch, W, live=8, slots=None):
            "load_factor": round(r.n_states / info.n_slots, 3),
            "roofline": roofline_of(r.n_states, r.n_states * bps, dt),
            "successor_buffer_bytes_per_state": round(successor_buffer_bytes_per_state(f, S), 1)}
+    traffic = measured_explore_traffic() if live == 8 and slots == W.LARGE_TABLE_SLOTS else None
+    out["roofline"]["traffic"] = traffic
+    out["roofline"]["traffic_unit"] = ("HBM bytes per exploration (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                       "scaled per access kind)")
+    if traffic:
+        out["roofline"]["measured_hbm_GBps"] = round(traffic / dt / 1e9, 1)
     return out
 
 
