@@ -348,6 +348,50 @@ gx_status gx_explore(const gx_network* net, gx_table* table, const gx_explore_op
 /* Release the arrays of a result filled by gx_explore.  NULL is accepted. */
 void gx_explore_result_free(gx_explore_result* result);
 
+/* ------------------------------------------------- exploration, no allocation */
+
+/* Device memory of gx_explore_noalloc: one array of this size per GPU the
+ * library runs on, held until the process ends. */
+#define GX_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+typedef struct {
+  uint64_t n_states, n_transitions;
+  uint32_t n_levels, words_per_state;
+  uint64_t n_deadlocks;
+} gx_explore_summary;
+
+/*
+ * For callers that cannot allocate (code near HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gx_explore with every
+ * device buffer it needs beyond the table in the library's static scratch
+ * array of GX_NOALLOC_SCRATCH_BYTES on the current device, and the results in
+ * the caller's host arrays.  It calls no hipMalloc, hipHostMalloc or hipFree
+ * and returns nothing that needs freeing.
+ *
+ *   net, table, opts  as for gx_explore (the table must be on the current
+ *                device; no safety monitor: opts->monitor_bad must be NULL).
+ *   level_counts  host, max_levels entries (max_levels >= 1): the level counts.
+ *   deadlocks     host, max_deadlocks x w words (nullable when max_deadlocks
+ *                 is 0): the deadlock states, sorted.
+ *   out           the counts.
+ *
+ * The scratch array holds a 64 KiB control block and four equal buffers of
+ * (GX_NOALLOC_SCRATCH_BYTES - 65792) / 4 bytes rounded down to a multiple of
+ * 256 (two frontiers, successors, deadlocks): 4,190,144 states of a 1-word
+ * slot, 2,095,072 of 2 words, 1,047,536 of 4 (3-word states take 4-word
+ * slots).
+ * A level, the successors of one state or the deadlocks beyond that, or more
+ * levels or deadlocks than the caller's arrays hold, give GX_ENOMEM (the
+ * table keeps what was stored).  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (two host threads, or two streams)
+ * race and must be serialised by the caller.  Synchronous.
+ * Errors: as gx_explore, plus GX_EINVAL for a monitor, null arrays or a
+ * table on another device.
+ */
+gx_status gx_explore_noalloc(const gx_network* net, gx_table* table, const gx_explore_opts* opts,
+                             uint64_t* level_counts, uint32_t max_levels, uint32_t* deadlocks,
+                             uint64_t max_deadlocks, gx_explore_summary* out);
+
 /* Static string naming a status code. */
 const char* gx_status_str(gx_status status);
 

@@ -35,6 +35,7 @@ EXPORTED = [
     "gx_batch_destroy", "gx_explore_batch", "gx_autotune",
     "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_get_stats",
     "gx_server_destroy", "gx_network_add_monitor", "gx_monitored_network_free",
+    "gx_explore_noalloc",
 ]
 
 
@@ -107,6 +108,12 @@ class _MonitoredNetwork(ctypes.Structure):
                 ("monitor_bad", ctypes.POINTER(ctypes.c_uint8)), ("owner", ctypes.c_void_p)]
 
 
+class _ExploreSummary(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_uint64), ("n_transitions", ctypes.c_uint64),
+                ("n_levels", ctypes.c_uint32), ("words_per_state", ctypes.c_uint32),
+                ("n_deadlocks", ctypes.c_uint64)]
+
+
 class _BatchOpts(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_void_p), ("hash_seed", ctypes.c_uint64),
                 ("max_hashes", ctypes.c_uint32), ("bucket_words", ctypes.c_uint32),
@@ -160,6 +167,10 @@ def lib() -> ctypes.CDLL:
         L.gx_table_dump.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
         L.gx_table_read_raw.restype = st
         L.gx_table_read_raw.argtypes = [vp, vp, u64, u64]
+        L.gx_explore_noalloc.restype = st
+        L.gx_explore_noalloc.argtypes = [ctypes.POINTER(_Network), vp,
+                                         ctypes.POINTER(_ExploreOpts), vp, u32, vp, u64,
+                                         ctypes.POINTER(_ExploreSummary)]
         L.gx_network_add_monitor.restype = st
         L.gx_network_add_monitor.argtypes = [ctypes.POINTER(_Network), ctypes.POINTER(_Monitor),
                                              ctypes.POINTER(_MonitoredNetwork)]
@@ -511,6 +522,26 @@ def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity:
     _check(lib().gx_explore(ctypes.byref(h.c), table.handle, ctypes.byref(opts),
                             ctypes.byref(res)), "gx_explore")
     return _take_result(res)
+
+
+def explore_noalloc(net, table: Table, *, max_levels: int = 4096, max_deadlocks: int = 1 << 20,
+                    frontier_capacity: int = 0, deadlock_capacity: int = 0, stream=None,
+                    local_dedup: bool = False) -> ExploreResult:
+    """gx_explore_noalloc: gx_explore with the library's static scratch array
+    for its device buffers and results in host arrays passed in (here numpy
+    arrays of max_levels and max_deadlocks entries)."""
+    h = _NetHolder(net)
+    w = table.info.words_per_state
+    levels = np.zeros(max(1, max_levels), dtype=np.uint64)
+    dead = np.zeros((max(1, max_deadlocks), w), dtype=np.uint32)
+    opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream),
+                        int(local_dedup), 0, 0, 0, None)
+    summ = _ExploreSummary()
+    _check(lib().gx_explore_noalloc(ctypes.byref(h.c), table.handle, ctypes.byref(opts),
+                                    levels.ctypes.data, max_levels, dead.ctypes.data,
+                                    max_deadlocks, ctypes.byref(summ)), "gx_explore_noalloc")
+    return ExploreResult(int(summ.n_states), int(summ.n_transitions), w,
+                         levels[: summ.n_levels].copy(), dead[: summ.n_deadlocks].copy())
 
 
 def gather_probe(buf, granule: int, n_reads: int, seed: int, sink, stream=None) -> None:

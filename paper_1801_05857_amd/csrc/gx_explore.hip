@@ -31,6 +31,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gx_small_kernel.hpp"
@@ -329,6 +330,91 @@ hipError_t grow(void** p, uint64_t* cap, uint64_t need, size_t elem, uint64_t ke
 }  // namespace
 }  // namespace gx
 
+namespace gx {
+
+// The control block of an exploration's buffers: the level counters (one
+// cache line each), what a small-level launch reports, the initial state's
+// slot and the network image.
+constexpr size_t kCtrWords = kCtrCount * kCtrSpread;
+constexpr size_t kBlockWords = kCtrWords + sizeof(SmallOut) / sizeof(uint64_t);
+constexpr size_t kControlBytes =
+    kBlockWords * sizeof(uint64_t) + 4 * sizeof(uint32_t) + kImgMaxWords * sizeof(uint32_t);
+
+// Where gx_explore_noalloc puts its results.
+struct FixedOut {
+  uint64_t* level_counts;
+  uint32_t max_levels;
+  uint32_t* deadlocks;
+  uint64_t max_deadlocks;
+  gx_explore_summary* summary;
+};
+
+// Level counts: a growing host vector, or (fixed) the caller's array, which
+// records an overflow instead of growing.
+class LevelList {
+ public:
+  explicit LevelList(FixedOut* f) : f_(f) {}
+  void push(uint64_t x) {
+    if (f_) {
+      if (n_ < f_->max_levels) f_->level_counts[n_] = x;
+      else overflow_ = true;
+    } else {
+      vec_.push_back(x);
+    }
+    ++n_;
+  }
+  uint64_t size() const { return n_; }
+  uint64_t at(uint64_t k) const { return f_ ? f_->level_counts[k] : vec_[k]; }
+  bool overflow() const { return overflow_; }
+
+ private:
+  FixedOut* f_;
+  std::vector<uint64_t> vec_;
+  uint64_t n_ = 0;
+  bool overflow_ = false;
+};
+
+template <int W>
+int cmp_records(const void* a, const void* b) {
+  const uint32_t* x = static_cast<const uint32_t*>(a);
+  const uint32_t* y = static_cast<const uint32_t*>(b);
+  for (int k = 0; k < W; ++k)
+    if (x[k] != y[k]) return x[k] < y[k] ? -1 : 1;
+  return 0;
+}
+
+// Results of a fixed (no-alloc) exploration into the caller's arrays: the
+// deadlock records (S words each on the device) are copied into the caller's
+// array in chunks through a small host buffer, cut to w words and sorted.
+gx_status finish_fixed(FixedOut& f, const LevelList& levels, uint64_t n_dead,
+                       uint64_t transitions, const uint32_t* dead, uint32_t S, uint32_t w) {
+  if (levels.overflow() || n_dead > f.max_deadlocks) return GX_ENOMEM;
+  constexpr uint64_t kChunk = 1024;
+  static thread_local uint32_t chunk[kChunk * 4];
+  for (uint64_t i0 = 0; i0 < n_dead; i0 += kChunk) {
+    const uint64_t n = std::min<uint64_t>(kChunk, n_dead - i0);
+    if (hipMemcpy(chunk, dead + i0 * S, n * S * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return GX_EDEVICE;
+    for (uint64_t i = 0; i < n; ++i)
+      for (uint32_t k = 0; k < w; ++k) f.deadlocks[(i0 + i) * w + k] = chunk[i * S + k];
+  }
+  static int (*const cmp[5])(const void*, const void*) = {nullptr, cmp_records<1>,
+                                                          cmp_records<2>, cmp_records<3>,
+                                                          cmp_records<4>};
+  if (n_dead) std::qsort(f.deadlocks, n_dead, w * sizeof(uint32_t), cmp[w]);
+  uint64_t n_states = 0;
+  for (uint64_t k = 0; k < levels.size(); ++k) n_states += levels.at(k);
+  f.summary->n_states = n_states;
+  f.summary->n_transitions = transitions;
+  f.summary->n_levels = static_cast<uint32_t>(levels.size());
+  f.summary->words_per_state = w;
+  f.summary->n_deadlocks = n_dead;
+  return GX_OK;
+}
+
+}  // namespace gx
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -368,28 +454,33 @@ void gx_explore_result_free(gx_explore_result* r) {
   r->states = nullptr;
 }
 
-gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* opts,
-                     gx_explore_result* out) {
-  if (!t || !out) return GX_EINVAL;
+// The exploration of gx_explore into table t, with its device buffers in eb.
+// fixed == nullptr: eb is the table's resident set, grown on demand, and the
+// result arrays are malloc'd into out.  fixed != nullptr (gx_explore_noalloc):
+// eb views preallocated memory that never grows (a buffer that would have to
+// is GX_ENOMEM), the control block's host side is plain memory, and the
+// level counts and deadlocks go to the caller's arrays in fixed.
+static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explore_opts* opts,
+                              gx_explore_buffers& eb, gx::FixedOut* fixed,
+                              gx_explore_result* out) {
   gx::NetImage ni;
   gx_status s = gx::compile_network(net, &ni);
   if (s != GX_OK) return s;
   if (ni.words != t->w) return GX_EINVAL;
   const bool monitor = opts && opts->monitor_bad;
-  if (monitor && opts->monitor_proc >= ni.field.size()) return GX_EINVAL;
+  if (monitor && (fixed || opts->monitor_proc >= ni.field.size())) return GX_EINVAL;
   const uint32_t S = t->S;
   const size_t state_bytes = S * sizeof(uint32_t);
   // 0: limited only by device memory
   const uint64_t max_cap = opts && opts->frontier_capacity ? opts->frontier_capacity : ~0ull;
   const uint64_t max_dead = opts && opts->deadlock_capacity ? opts->deadlock_capacity : ~0ull;
   hipStream_t stream = opts ? static_cast<hipStream_t>(opts->hip_stream) : nullptr;
-  gx_explore_buffers& eb = t->eb;
   const uint64_t max_succ = std::max<uint64_t>(1, ni.max_succ);
 
   auto grow_buf = [&](uint32_t** p, uint64_t* cap, uint64_t need, uint64_t keep,
                       uint64_t limit) -> gx_status {
     if (*cap >= need && *p) return GX_OK;
-    if (need > limit) return GX_ENOMEM;
+    if (need > limit || fixed) return GX_ENOMEM;
     const uint64_t want = std::min<uint64_t>(limit, std::max<uint64_t>(need, 1u << 16));
     const hipError_t e = gx::grow(reinterpret_cast<void**>(p), cap, want, state_bytes, keep,
                                   stream, limit);
@@ -402,10 +493,9 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   const uint32_t img_stride = (img_words + 3) & ~3u;
   // the control block: the level's counters, what a small-level launch
   // reports (read back together), the initial state's slot, the image
-  constexpr size_t kCtrWords = gx::kCtrCount * gx::kCtrSpread;
-  constexpr size_t kBlockWords = kCtrWords + sizeof(gx::SmallOut) / sizeof(uint64_t);
-  constexpr size_t kControlBytes =
-      kBlockWords * sizeof(uint64_t) + 4 * sizeof(uint32_t) + gx::kImgMaxWords * sizeof(uint32_t);
+  constexpr size_t kCtrWords = gx::kCtrWords;
+  constexpr size_t kBlockWords = gx::kBlockWords;
+  constexpr size_t kControlBytes = gx::kControlBytes;
   if (img_stride > gx::kImgMaxWords) return GX_EINVAL;
   if (!eb.ctr && (hipMalloc(&eb.ctr, kControlBytes) != hipSuccess ||
                   hipHostMalloc(&eb.ctr_host, kControlBytes) != hipSuccess ||
@@ -549,7 +639,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   // most).  The room is tracked from these worst-case bounds; only when it is
   // short of a full slice is the exact fill read back (one synchronisation),
   // and the buffers grow, keeping their contents, to hold a full slice.
-  std::vector<uint64_t> levels{1};
+  gx::LevelList levels(fixed);
+  levels.push(1);
   uint64_t n_in = 1;
   int cur = 0;
   uint64_t dead_known = 0;
@@ -616,7 +707,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
         if (small_out->init_status == gx::kFull) return GX_ETABLEFULL;
         if (small_out->init_status != gx::kNew) return GX_EINVAL;
       }
-      for (uint64_t k = 0; k < small_out->n_levels; ++k) levels.push_back(small_out->levels[k]);
+      for (uint64_t k = 0; k < small_out->n_levels; ++k) levels.push(small_out->levels[k]);
       dead_known = ctr(gx::kCtrDead);
       if (dead_known > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;
       n_in = small_out->n_in;
@@ -697,7 +788,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     if ((s = read_ctr()) != GX_OK) return s;
     dead_known = ctr(gx::kCtrDead);
     n_in = ctr(gx::kCtrTail);
-    if (n_in) levels.push_back(n_in);
+    if (n_in) levels.push(n_in);
     if (monitor && n_in) {
       // scan the level just completed; if the record buffer was short, grow
       // it (keeping earlier levels' records) and scan the level again
@@ -727,6 +818,7 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   }
   const uint64_t n_dead = ctr(gx::kCtrDead);
   if (n_dead > std::min<uint64_t>(eb.dead_cap, max_dead)) return GX_ENOMEM;
+  if (fixed) return gx::finish_fixed(*fixed, levels, n_dead, ctr(gx::kCtrTrans), eb.dead, S, t->w);
   std::vector<uint32_t> raw(n_dead * S);
   if (n_dead && hipMemcpy(raw.data(), eb.dead, raw.size() * sizeof(uint32_t),
                           hipMemcpyDeviceToHost) != hipSuccess)
@@ -746,9 +838,9 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     return GX_ENOMEM;
   }
   uint64_t n_states = 0;
-  for (size_t k = 0; k < levels.size(); ++k) {
-    lv[k] = levels[k];
-    n_states += levels[k];
+  for (uint64_t k = 0; k < levels.size(); ++k) {
+    lv[k] = levels.at(k);
+    n_states += levels.at(k);
   }
   for (uint64_t i = 0; i < n_dead; ++i)
     for (uint32_t k = 0; k < t->w; ++k) dd[i * t->w + k] = dl[i][k];
@@ -763,6 +855,8 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
   out->n_violations = 0;
   out->violations = nullptr;
   out->violation_level = viol_level;
+  out->reserved = 0;
+  out->states = nullptr;
   if (monitor) {
     std::vector<uint32_t> vraw(viol_total * S);
     if (viol_total && hipMemcpy(vraw.data(), eb.viol, vraw.size() * sizeof(uint32_t),
@@ -788,6 +882,81 @@ gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* 
     out->violations = vv;
   }
   return GX_OK;
+}
+
+gx_status gx_explore(const gx_network* net, gx_table* t, const gx_explore_opts* opts,
+                     gx_explore_result* out) {
+  if (!t || !out) return GX_EINVAL;
+  return explore_impl(net, t, opts, t->eb, nullptr, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------- no-alloc exploration
+// Every device buffer gx_explore_noalloc needs beyond the table: one array
+// per GPU the library runs on, held until the process ends.  In host code
+// the name `scratch` is only a stand-in; its device address comes from
+// hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) uint8_t scratch[GX_NOALLOC_SCRATCH_BYTES];
+
+namespace gx {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices] = {};
+
+// The device address of this GPU's scratch array, looked up once per device
+// (with that device current) and kept.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    scratch_dev[device] = p;
+  }
+  return scratch_dev[device];
+}
+
+}  // namespace
+}  // namespace gx
+
+extern "C" {
+
+gx_status gx_explore_noalloc(const gx_network* net, gx_table* t, const gx_explore_opts* opts,
+                             uint64_t* level_counts, uint32_t max_levels, uint32_t* deadlocks,
+                             uint64_t max_deadlocks, gx_explore_summary* out) {
+  if (!t || !out || !level_counts || max_levels == 0 || (max_deadlocks && !deadlocks))
+    return GX_EINVAL;
+  if (opts && opts->monitor_bad) return GX_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GX_EDEVICE;
+  if (dev != t->device) return GX_EINVAL;
+  char* base = static_cast<char*>(gx::scratch_address(dev));
+  if (!base) return GX_EDEVICE;
+  // control block | status | frontier 0 | frontier 1 | successors | deadlocks
+  constexpr uint64_t kCtl = (gx::kControlBytes + 65535) / 65536 * 65536;
+  constexpr uint64_t kRegion = (GX_NOALLOC_SCRATCH_BYTES - kCtl - 256) / 4 / 256 * 256;
+  static_assert(kCtl + 256 + 4 * kRegion <= GX_NOALLOC_SCRATCH_BYTES, "scratch layout");
+  const uint64_t cap = kRegion / (t->S * sizeof(uint32_t));
+  static thread_local uint64_t host_block[(gx::kControlBytes + 7) / 8];
+  gx_explore_buffers eb;  // views of the scratch array; never grown
+  eb.ctr = reinterpret_cast<uint64_t*>(base);
+  eb.ctr_host = host_block;
+  eb.status = reinterpret_cast<uint8_t*>(base + kCtl);
+  char* r = base + kCtl + 256;
+  eb.f[0] = reinterpret_cast<uint32_t*>(r);
+  eb.f[1] = reinterpret_cast<uint32_t*>(r + kRegion);
+  eb.succ = reinterpret_cast<uint32_t*>(r + 2 * kRegion);
+  eb.dead = reinterpret_cast<uint32_t*>(r + 3 * kRegion);
+  eb.f_cap[0] = eb.f_cap[1] = eb.succ_cap = eb.dead_cap = cap;
+  gx::FixedOut f{level_counts, max_levels, deadlocks, max_deadlocks, out};
+  gx_explore_result unused{};
+  return explore_impl(net, t, opts, eb, &f, &unused);
 }
 
 }  // extern "C"
