@@ -148,6 +148,10 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
                 "g.build()'` (or paper_1801_05857_amd/build.py); there is no fallback path")
+        # torch's HIP runtime is loaded first, so that the library binds to
+        # the same one: loaded the other way round, torch finds no GPU once
+        # the library has touched the device
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         st, vp, u32, u64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
         L.gx_table_create.restype = st
