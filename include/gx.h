@@ -398,14 +398,22 @@ const char* gx_status_str(gx_status status);
 /* ------------------------------------------------------------ batches */
 
 /*
- * Batched exploration: many networks (instances) explored by one persistent
- * kernel launch per kernel class, each instance with its own table partition
- * carved from one allocation.  Every instance follows exactly the
- * single-exploration semantics of gx_explore (Sec. 3); instances advance
- * level by level independently, workgroups pulling (instance, level, tile)
- * work from a device-side queue.  Instances that share a kernel
- * configuration (slot words, bucket words, subgroup, keys per subgroup) form a
- * class; classes run concurrently on their own streams.
+ * Batched exploration: many networks (instances) explored together, each
+ * with its own table partition carved from one allocation per kernel class.
+ * Every instance follows exactly the single-exploration semantics of
+ * gx_explore (Sec. 3).  Instances that share a kernel configuration (slot
+ * words, bucket words, subgroup, keys per subgroup) form a class.  Two
+ * schedules:
+ *   stepped (the default): every unfinished instance advances one BFS level
+ *     per step; a step is one launch per class over the current levels of
+ *     all its unfinished instances, then one read-back of their next-level
+ *     sizes.  gx_batch_run drives the steps from the calling thread and
+ *     returns when every instance has finished.
+ *   persistent (use_graph or persistent nonzero): one persistent launch per
+ *     class, classes concurrently on their own streams; instances advance
+ *     independently, workgroups pulling (instance, level, tile) work from a
+ *     device-side queue; gx_batch_run only enqueues, and a whole run can be
+ *     captured in a hipGraph.
  */
 typedef struct gx_batch gx_batch;
 
@@ -420,23 +428,25 @@ typedef struct {
                                  (4 with buckets of at most 32 words; an
                                  explicit 4 caps an autotuned bucket at 32)   */
   uint32_t keys_per_subgroup; /* 0 -> 1, else 1|2                             */
-  uint32_t use_graph;         /* nonzero: gx_batch_create captures a whole run
-                                 (clears, resets and every launch) in a hipGraph
-                                 and gx_batch_run replays it                   */
+  uint32_t use_graph;         /* nonzero: the persistent schedule, and
+                                 gx_batch_create captures a whole run (clears,
+                                 resets and every launch) in a hipGraph that
+                                 gx_batch_run replays                         */
   uint32_t max_levels;        /* BFS levels per instance; 0 -> 4096.  An
-                                 instance deeper than this gets GX_ENOMEM.  The
-                                 device work queue holds instances x
-                                 max_levels entries of 32 bytes, so every
-                                 level of every instance fits; instances x
-                                 max_levels must stay below 2^31 (else
-                                 GX_EINVAL)                                   */
+                                 instance deeper than this gets GX_ENOMEM.  In
+                                 the persistent schedule the device work queue
+                                 holds instances x max_levels entries of 32
+                                 bytes, so every level of every instance fits;
+                                 instances x max_levels must then stay below
+                                 2^31 (else GX_EINVAL)                        */
   uint64_t deadlock_capacity; /* deadlock records per class; 0 -> min(sum of
                                  capacities, 2^26)                             */
   void* hip_stream;           /* stream used by gx_explore_batch               */
   uint32_t keep_states;       /* nonzero: gx_batch_results also returns every
                                  instance's reachable states (its table
                                  partition's contents) in outs[i].states      */
-  uint32_t reserved;
+  uint32_t persistent;        /* nonzero: the persistent schedule without a
+                                 graph; 0 (and use_graph 0): stepped          */
 } gx_batch_opts;
 
 /* Compile every network (argument errors before device work), choose each
@@ -444,8 +454,11 @@ typedef struct {
 gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opts* opts,
                           gx_batch** out);
 
-/* Clear every table and explore every instance from its initial state.
- * Stream-ordered; may be called again to repeat the whole batch. */
+/* Clear every table and explore every instance from its initial state, on
+ * hip_stream after the work already queued there.  Stepped schedule: returns
+ * when the run has finished (the calling thread drives its steps).
+ * Persistent schedule: enqueues the run and returns.  May be called again to
+ * repeat the whole batch. */
 gx_status gx_batch_run(gx_batch* batch, void* hip_stream);
 
 /* Wait for the last run and fill outs[i] / inst_status[i] for every instance

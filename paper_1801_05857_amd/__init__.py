@@ -120,7 +120,7 @@ class _BatchOpts(ctypes.Structure):
                 ("subgroup", ctypes.c_uint32), ("keys_per_subgroup", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("max_levels", ctypes.c_uint32),
                 ("deadlock_capacity", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
-                ("keep_states", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("keep_states", ctypes.c_uint32), ("persistent", ctypes.c_uint32)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -565,12 +565,14 @@ def autotune(words_per_state: int, load_factor: float = 0.5) -> tuple[int, int, 
 
 
 class Batch:
-    """gx_batch: many explorations in one persistent launch per kernel class."""
+    """gx_batch: many explorations together, level-synchronous steps over all
+    unfinished instances (the default), or one persistent launch per kernel
+    class pulling work from a device queue (``persistent`` or ``use_graph``)."""
 
     def __init__(self, nets, capacity, *, hash_seed: int = 0, max_hashes: int = 0,
                  bucket_words: int = 0, subgroup: int = 0, keys_per_subgroup: int = 0,
                  use_graph: bool = False, max_levels: int = 0, deadlock_capacity: int = 0,
-                 keep_states: bool = False):
+                 keep_states: bool = False, persistent: bool = False):
         self.n = len(nets)
         holders = [_NetHolder(net) for net in nets]
         arr = (_Network * self.n)(*[h.c for h in holders])
@@ -579,7 +581,7 @@ class Batch:
             raise ValueError("one capacity per network")
         opts = _BatchOpts(cap.ctypes.data, hash_seed, max_hashes, bucket_words, subgroup,
                           keys_per_subgroup, int(use_graph), max_levels, deadlock_capacity, None,
-                          int(keep_states), 0)
+                          int(keep_states), int(persistent))
         h = ctypes.c_void_p()
         _check(lib().gx_batch_create(arr, self.n, ctypes.byref(opts), ctypes.byref(h)),
                "gx_batch_create")

@@ -1,9 +1,20 @@
-// Batched exploration (many networks in one persistent launch per kernel
-// class) and the find-or-put autotuner.
+// Batched exploration (many networks explored together, each in its own table
+// partition) and the find-or-put autotuner.
+//
+// Two schedules.  Stepped (the default): every unfinished instance advances
+// one BFS level per step; a step is one multi-instance launch per kernel
+// class (the server's step kernel over the concatenated tiles of the class's
+// current levels), a summary kernel per class that copies each instance's
+// next-level size and flags into a compact array and clears its tail, and
+// one read-back of those arrays; gx_batch_run returns when every instance has
+// finished.  Persistent (with use_graph or persistent): one persistent launch
+// per class pulls (instance, level, tile) work from a device queue with no
+// host involvement, so a whole run can be captured in a hipGraph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <array>
+#include <cstddef>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -15,6 +26,7 @@
 #include <vector>
 
 #include "gx_batch_kernel.hpp"
+#include "gx_serve_kernel.hpp"
 
 namespace gx {
 
@@ -38,6 +50,21 @@ extern template hipError_t batch_launch<4>(uint32_t, uint32_t, uint32_t, const B
 extern template int batch_resident<1>(uint32_t, uint32_t, uint32_t, size_t);
 extern template int batch_resident<2>(uint32_t, uint32_t, uint32_t, size_t);
 extern template int batch_resident<4>(uint32_t, uint32_t, uint32_t, size_t);
+template <int S>
+hipError_t batch_init(uint32_t B, uint32_t G, uint32_t U, const BatchArgs& a, hipStream_t s);
+extern template hipError_t batch_init<1>(uint32_t, uint32_t, uint32_t, const BatchArgs&,
+                                         hipStream_t);
+extern template hipError_t batch_init<2>(uint32_t, uint32_t, uint32_t, const BatchArgs&,
+                                         hipStream_t);
+extern template hipError_t batch_init<4>(uint32_t, uint32_t, uint32_t, const BatchArgs&,
+                                         hipStream_t);
+// instantiated in gx_serve_s1.hip, gx_serve_s2.hip, gx_serve_s4.hip
+extern template hipError_t serve_launch<1>(uint32_t, uint32_t, uint32_t, const ServeArgs&,
+                                           uint32_t, size_t, hipStream_t);
+extern template hipError_t serve_launch<2>(uint32_t, uint32_t, uint32_t, const ServeArgs&,
+                                           uint32_t, size_t, hipStream_t);
+extern template hipError_t serve_launch<4>(uint32_t, uint32_t, uint32_t, const ServeArgs&,
+                                           uint32_t, size_t, hipStream_t);
 
 namespace {
 
@@ -67,6 +94,18 @@ __global__ void tune_keys_kernel(uint32_t* keys, uint32_t S, uint64_t n, uint64_
     keys[i * S + k] = static_cast<uint32_t>((k & 1) ? (x >> 33) : (x & 0x7FFFFFFFu)) ^ k;
 }
 
+// After a step of the stepped schedule: instance k's next-level size and
+// flags to sum[2k], sum[2k + 1]; its next-level tail cleared for the step
+// after.
+__global__ void batch_step_summary_kernel(BatchState* state, uint32_t n, uint64_t* sum) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint64_t* c = state[k].ctr;
+  sum[2 * k] = c[kCtrTail * kCtrSpread];
+  sum[2 * k + 1] = c[kCtrFlags * kCtrSpread];
+  c[kCtrTail * kCtrSpread] = 0;
+}
+
 }  // namespace
 }  // namespace gx
 
@@ -76,6 +115,7 @@ struct gx_batch {
     std::vector<uint32_t> members;  // instance ids
     // device
     gx::BatchInst* inst = nullptr;
+    std::vector<gx::BatchInst> h_inst;  // host copy of inst
     gx::BatchState* state = nullptr;
     gx::BatchState* state_init = nullptr;
     gx::BatchEntry* queue = nullptr;
@@ -98,6 +138,12 @@ struct gx_batch {
     size_t lds = 0;
     hipStream_t side = nullptr;
     hipEvent_t ev_done = nullptr;
+    // stepped schedule: job descriptors (device, pinned staging) and the
+    // per-step summary (device, pinned read-back), nc entries each
+    gx::ServeJob* d_jobs = nullptr;
+    gx::ServeJob* h_jobs = nullptr;
+    uint64_t* d_sum = nullptr;
+    uint64_t* h_sum = nullptr;
   };
   int device = 0;
   uint32_t n = 0;
@@ -112,9 +158,13 @@ struct gx_batch {
   std::vector<Class> classes;
   hipEvent_t ev_fork = nullptr;
   bool use_graph = false;
+  bool stepped = false;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture_stream = nullptr;
   bool ran = false;
+  // the last stepped run: per instance, its level counts and status
+  std::vector<std::vector<uint64_t>> step_levels;
+  std::vector<gx_status> step_status;
 };
 
 namespace gx {
@@ -137,6 +187,10 @@ void free_batch(gx_batch* b) {
       if (p) (void)hipFree(p);
     if (c.side) (void)hipStreamDestroy(c.side);
     if (c.ev_done) (void)hipEventDestroy(c.ev_done);
+    if (c.d_jobs) (void)hipFree(c.d_jobs);
+    if (c.d_sum) (void)hipFree(c.d_sum);
+    if (c.h_jobs) (void)hipHostFree(c.h_jobs);
+    if (c.h_sum) (void)hipHostFree(c.h_sum);
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->hc) (void)hipFree(b->hc);
@@ -146,6 +200,24 @@ void free_batch(gx_batch* b) {
 template <typename T>
 hipError_t dmalloc(T** p, uint64_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), std::max<uint64_t>(1, count) * sizeof(T));
+}
+
+BatchArgs class_args(const gx_batch::Class& c) {
+  BatchArgs a;
+  a.inst = c.inst;
+  a.state = c.state;
+  a.queue = c.queue;
+  a.queue_cap = c.queue_cap;
+  a.g = c.g;
+  a.n = static_cast<uint32_t>(c.members.size());
+  a.img = c.img;
+  a.img_stride = c.img_stride;
+  a.dead = c.dead;
+  a.dead_tag = c.dead_tag;
+  a.dead_cap = c.dead_cap;
+  a.spin_limit = kSpinLimit;
+  a.init_states = c.init_states;
+  return a;
 }
 
 // Enqueue one full run of the batch on `stream`: reset every class, then the
@@ -170,20 +242,7 @@ hipError_t enqueue_run(gx_batch* b, hipStream_t stream) {
         (e = hipMemcpyAsync(c.g, c.g_init, sizeof(BatchGlobal), hipMemcpyDeviceToDevice,
                             c.side)) != hipSuccess)
       return e;
-    BatchArgs a;
-    a.inst = c.inst;
-    a.state = c.state;
-    a.queue = c.queue;
-    a.queue_cap = c.queue_cap;
-    a.g = c.g;
-    a.n = nc;
-    a.img = c.img;
-    a.img_stride = c.img_stride;
-    a.dead = c.dead;
-    a.dead_tag = c.dead_tag;
-    a.dead_cap = c.dead_cap;
-    a.spin_limit = kSpinLimit;
-    a.init_states = c.init_states;
+    const BatchArgs a = class_args(c);
     switch (c.S) {
       case 1: e = batch_launch<1>(c.B, c.G, c.U, a, c.grid, c.lds, c.side); break;
       case 2: e = batch_launch<2>(c.B, c.G, c.U, a, c.grid, c.lds, c.side); break;
@@ -194,6 +253,131 @@ hipError_t enqueue_run(gx_batch* b, hipStream_t stream) {
     if ((e = hipStreamWaitEvent(stream, c.ev_done, 0)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// One whole run under the stepped schedule on `stream` (see the top of this
+// file); synchronous.  The per-instance outcome goes to b->step_levels and
+// b->step_status.
+gx_status run_stepped(gx_batch* b, hipStream_t stream) {
+  const size_t nk = b->classes.size();
+  std::vector<std::vector<uint64_t>> n_in(nk);
+  std::vector<std::vector<uint8_t>> cur(nk), live(nk);
+  b->step_levels.assign(b->n, std::vector<uint64_t>(1, 1));
+  b->step_status.assign(b->n, GX_OK);
+  for (size_t ci = 0; ci < nk; ++ci) {
+    gx_batch::Class& c = b->classes[ci];
+    const uint32_t nc = static_cast<uint32_t>(c.members.size());
+    n_in[ci].assign(nc, 1);
+    cur[ci].assign(nc, 0);
+    live[ci].assign(nc, 1);
+    // clear the tables, reset the counters and the shared deadlock count,
+    // put and insert every initial state
+    if (fill_words(c.tables, c.table_words, kEmpty, b->device, stream) != hipSuccess ||
+        hipMemcpyAsync(c.state, c.state_init, nc * sizeof(BatchState), hipMemcpyDeviceToDevice,
+                       stream) != hipSuccess ||
+        hipMemcpyAsync(c.g, c.g_init, sizeof(BatchGlobal), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess)
+      return GX_EDEVICE;
+    const BatchArgs a = class_args(c);
+    hipError_t e;
+    switch (c.S) {
+      case 1: e = batch_init<1>(c.B, c.G, c.U, a, stream); break;
+      case 2: e = batch_init<2>(c.B, c.G, c.U, a, stream); break;
+      default: e = batch_init<4>(c.B, c.G, c.U, a, stream); break;
+    }
+    if (e != hipSuccess) return GX_EDEVICE;
+  }
+  while (true) {
+    bool any = false;
+    for (size_t ci = 0; ci < nk; ++ci) {
+      gx_batch::Class& c = b->classes[ci];
+      const uint32_t nc = static_cast<uint32_t>(c.members.size());
+      uint32_t n_jobs = 0;
+      uint64_t tiles = 0;
+      for (uint32_t k = 0; k < nc; ++k) {
+        if (!live[ci][k]) continue;
+        // the descriptor from the instance's static part (BatchInst, mirrored
+        // on the host at creation) and its current level
+        ServeJob& x = c.h_jobs[n_jobs++];
+        const BatchInst& in = c.h_inst[k];
+        x.t = in.t;
+        x.img_off = in.img_off;
+        x.img_words = in.img_words;
+        x.frontier_in = in.f[cur[ci][k]];
+        x.n_in = n_in[ci][k];
+        x.frontier_out = in.f[cur[ci][k] ^ 1];
+        x.cap_out = in.cap;
+        x.dead = c.dead;
+        x.dead_cap = c.dead_cap;
+        x.ctr = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(c.state) +
+                                            k * sizeof(BatchState) + offsetof(BatchState, ctr));
+        x.tile_begin = tiles;
+        x.dead_ctr = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(c.g) +
+                                                 offsetof(BatchGlobal, dead_used));
+        x.dead_tag = c.dead_tag;
+        x.tag = k;
+        x.pad = 0;
+        tiles += (n_in[ci][k] + 255) / 256;
+      }
+      if (n_jobs == 0) continue;
+      any = true;
+      if (tiles > 0x7FFFFFFFull) return GX_EINVAL;
+      ServeArgs sa;
+      sa.jobs = c.d_jobs;
+      sa.n_jobs = n_jobs;
+      sa.img = c.img;
+      sa.img_stride = c.img_stride;
+      hipError_t e = hipMemcpyAsync(c.d_jobs, c.h_jobs, n_jobs * sizeof(ServeJob),
+                                    hipMemcpyHostToDevice, stream);
+      if (e == hipSuccess) {
+        const uint32_t grid = static_cast<uint32_t>(tiles);
+        switch (c.S) {
+          case 1: e = serve_launch<1>(c.B, c.G, c.U, sa, grid, c.lds, stream); break;
+          case 2: e = serve_launch<2>(c.B, c.G, c.U, sa, grid, c.lds, stream); break;
+          default: e = serve_launch<4>(c.B, c.G, c.U, sa, grid, c.lds, stream); break;
+        }
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(batch_step_summary_kernel, dim3((nc + 255) / 256), dim3(256), 0, stream,
+                           c.state, nc, c.d_sum);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c.h_sum, c.d_sum, 2ull * nc * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                           stream);
+      if (e != hipSuccess) return GX_EDEVICE;
+    }
+    if (!any) break;
+    // one synchronisation per step: the staged descriptors of this step are
+    // reused only after it
+    if (hipStreamSynchronize(stream) != hipSuccess) return GX_EDEVICE;
+    for (size_t ci = 0; ci < nk; ++ci) {
+      gx_batch::Class& c = b->classes[ci];
+      const uint32_t nc = static_cast<uint32_t>(c.members.size());
+      for (uint32_t k = 0; k < nc; ++k) {
+        if (!live[ci][k]) continue;
+        const uint32_t i = c.members[k];
+        const uint64_t n_next = c.h_sum[2 * k], flags = c.h_sum[2 * k + 1];
+        std::vector<uint64_t>& L = b->step_levels[i];
+        gx_status st = GX_OK;
+        bool done = true;
+        if (flags & kFlagTableFull) st = GX_ETABLEFULL;
+        else if (flags) st = GX_ENOMEM;
+        else if (n_next == 0) st = GX_OK;
+        else if (L.size() >= b->max_levels) st = GX_ENOMEM;  // deeper than max_levels
+        else done = false;
+        if (done) {
+          live[ci][k] = 0;
+          b->step_status[i] = st;
+        } else {
+          L.push_back(n_next);
+          n_in[ci][k] = n_next;
+          cur[ci][k] ^= 1;
+        }
+      }
+    }
+  }
+  return GX_OK;
 }
 
 bool valid_pow2(uint32_t x, uint32_t lo, uint32_t hi) {
@@ -320,7 +504,9 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
   }
   b->n = n;
   b->max_levels = opts->max_levels ? opts->max_levels : gx::kDefaultMaxLevels;
-  if (static_cast<uint64_t>(n) * b->max_levels >= (uint64_t(1) << 31)) {
+  b->use_graph = opts->use_graph != 0;
+  b->stepped = !b->use_graph && !opts->persistent;
+  if (!b->stepped && static_cast<uint64_t>(n) * b->max_levels >= (uint64_t(1) << 31)) {
     delete b;
     return GX_EINVAL;
   }
@@ -418,8 +604,9 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
     c.table_words = tw;
     c.img_stride = static_cast<uint32_t>(gx::align_up(max_img, 4));
     // every instance publishes at most one entry per level, so the queue
-    // never overflows (checked against 2^31 entries when the batch is made)
-    c.queue_cap = nc * b->max_levels;
+    // never overflows (checked against 2^31 entries when the batch is made);
+    // the stepped schedule has no queue
+    c.queue_cap = b->stepped ? 0 : nc * b->max_levels;
     uint64_t sum_cap = 0;
     for (uint32_t i : c.members) sum_cap += opts->capacity[i];
     c.dead_cap = opts->deadlock_capacity ? opts->deadlock_capacity
@@ -427,11 +614,17 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
     if (gx::dmalloc(&c.tables, tw) != hipSuccess || gx::dmalloc(&c.frontiers, fw) != hipSuccess ||
         gx::dmalloc(&c.inst, nc) != hipSuccess || gx::dmalloc(&c.state, nc) != hipSuccess ||
         gx::dmalloc(&c.state_init, nc) != hipSuccess ||
-        gx::dmalloc(&c.queue, c.queue_cap) != hipSuccess ||
-        gx::dmalloc(&c.queue_init, nc) != hipSuccess || gx::dmalloc(&c.g, 1) != hipSuccess ||
+        (!b->stepped && (gx::dmalloc(&c.queue, c.queue_cap) != hipSuccess ||
+                         gx::dmalloc(&c.queue_init, nc) != hipSuccess)) ||
+        (b->stepped && (gx::dmalloc(&c.d_jobs, nc) != hipSuccess ||
+                        gx::dmalloc(&c.d_sum, 2ull * nc) != hipSuccess ||
+                        hipHostMalloc(&c.h_jobs, nc * sizeof(gx::ServeJob)) != hipSuccess ||
+                        hipHostMalloc(&c.h_sum, 2ull * nc * sizeof(uint64_t)) != hipSuccess)) ||
+        gx::dmalloc(&c.g, 1) != hipSuccess ||
         gx::dmalloc(&c.g_init, 1) != hipSuccess || gx::dmalloc(&c.img, imgw) != hipSuccess ||
         gx::dmalloc(&c.init_states, static_cast<uint64_t>(nc) * S) != hipSuccess ||
-        gx::dmalloc(&c.levels, static_cast<uint64_t>(nc) * b->max_levels) != hipSuccess ||
+        (!b->stepped &&
+         gx::dmalloc(&c.levels, static_cast<uint64_t>(nc) * b->max_levels) != hipSuccess) ||
         gx::dmalloc(&c.dead, c.dead_cap * S) != hipSuccess ||
         gx::dmalloc(&c.dead_tag, c.dead_cap) != hipSuccess ||
         gx::dmalloc(&c.stats, 2 * gx::kNumCounters) != hipSuccess ||
@@ -464,7 +657,7 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
       in.f[0] = c.frontiers + fr_off[k];
       in.f[1] = c.frontiers + fr_off[k] + fcap;
       in.cap = opts->capacity[i];
-      in.levels = c.levels + static_cast<uint64_t>(k) * b->max_levels;
+      in.levels = c.levels ? c.levels + static_cast<uint64_t>(k) * b->max_levels : nullptr;
       in.max_levels = b->max_levels;
       std::copy(imgs[i].begin(), imgs[i].end(), himg.begin() + img_off[k]);
       for (uint32_t x = 0; x < words[i]; ++x) hinit[static_cast<size_t>(k) * S + x] = inits[i][x];
@@ -481,8 +674,8 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
     if (hipMemcpy(c.inst, hi.data(), nc * sizeof(gx::BatchInst), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c.state_init, hs.data(), nc * sizeof(gx::BatchState), hipMemcpyHostToDevice) !=
             hipSuccess ||
-        hipMemcpy(c.queue_init, he.data(), nc * sizeof(gx::BatchEntry), hipMemcpyHostToDevice) !=
-            hipSuccess ||
+        (!b->stepped && hipMemcpy(c.queue_init, he.data(), nc * sizeof(gx::BatchEntry),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemcpy(c.g_init, &hg, sizeof(hg), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c.img, himg.data(), himg.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -491,6 +684,7 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
       gx::free_batch(b);
       return GX_EDEVICE;
     }
+    c.h_inst = std::move(hi);
     c.lds = (c.img_stride + gx::kStageWords) * sizeof(uint32_t);
     int per_cu = 1;
     switch (S) {
@@ -518,7 +712,6 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
                                   static_cast<uint32_t>(c.grid * share + 0.5));
     }
   }
-  b->use_graph = opts->use_graph != 0;
   if (b->use_graph) {
     hipGraph_t graph = nullptr;
     if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess ||
@@ -557,6 +750,12 @@ gx_status gx_batch_instance_config(const gx_batch* b, uint32_t i, uint32_t* buck
 gx_status gx_batch_run(gx_batch* b, void* hip_stream) {
   if (!b) return GX_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (b->stepped) {
+    const gx_status st = gx::run_stepped(b, s);
+    if (st != GX_OK) return st;
+    b->ran = true;
+    return GX_OK;
+  }
   hipError_t e;
   if (b->use_graph) {
     e = hipGraphLaunch(b->exec, s);
@@ -579,12 +778,12 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
     const uint32_t nc = static_cast<uint32_t>(c.members.size());
     const uint32_t S = c.S;
     std::vector<gx::BatchState> hs(nc);
-    std::vector<uint64_t> lv(static_cast<size_t>(nc) * b->max_levels);
+    std::vector<uint64_t> lv(b->stepped ? 0 : static_cast<size_t>(nc) * b->max_levels);
     gx::BatchGlobal hg;
     if (hipMemcpy(hs.data(), c.state, nc * sizeof(gx::BatchState), hipMemcpyDeviceToHost) !=
             hipSuccess ||
-        hipMemcpy(lv.data(), c.levels, lv.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
-            hipSuccess ||
+        (!b->stepped && hipMemcpy(lv.data(), c.levels, lv.size() * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost) != hipSuccess) ||
         hipMemcpy(&hg, c.g, sizeof(hg), hipMemcpyDeviceToHost) != hipSuccess)
       return GX_EDEVICE;
     const uint64_t n_rec = std::min<uint64_t>(hg.dead_used, c.dead_cap);
@@ -608,17 +807,20 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
       outs[i] = gx_explore_result{};  // no safety monitor in batches
       outs[i].violation_level = 0xFFFFFFFFu;
       gx_status s = GX_OK;
-      if (!st.done || hg.abort)
+      if (b->stepped)
+        s = b->step_status[i];
+      else if (!st.done || hg.abort)
         s = GX_EDEVICE;
       else if (flags & gx::kFlagTableFull)
         s = GX_ETABLEFULL;
       else if (flags)
         s = GX_ENOMEM;
-      else if (per[k].size() != st.ctr[gx::kCtrDead * gx::kCtrSpread])
+      if (s == GX_OK && per[k].size() != st.ctr[gx::kCtrDead * gx::kCtrSpread])
         s = GX_ENOMEM;  // deadlock records overflowed
       inst_status[i] = s;
       if (s != GX_OK) continue;
-      const uint32_t n_levels = st.level + 1;
+      const uint32_t n_levels =
+          b->stepped ? static_cast<uint32_t>(b->step_levels[i].size()) : st.level + 1;
       uint64_t* L = static_cast<uint64_t*>(std::malloc(sizeof(uint64_t) * n_levels));
       auto& dl = per[k];
       std::sort(dl.begin(), dl.end());
@@ -631,7 +833,9 @@ gx_status gx_batch_results(gx_batch* b, gx_explore_result* outs, gx_status* inst
       }
       uint64_t total = 0;
       for (uint32_t l = 0; l < n_levels; ++l) {
-        L[l] = l == 0 ? 1 : lv[static_cast<size_t>(k) * b->max_levels + l];
+        L[l] = l == 0         ? 1
+               : b->stepped ? b->step_levels[i][l]
+                            : lv[static_cast<size_t>(k) * b->max_levels + l];
         total += L[l];
       }
       for (size_t r = 0; r < dl.size(); ++r)

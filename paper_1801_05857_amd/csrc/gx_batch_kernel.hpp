@@ -266,6 +266,10 @@ struct BatchKernels {  // init + persistent launch of one (S, B, G, U) class
     hipLaunchKernelGGL((batch_explore_kernel<S, B, G, U>), dim3(grid), dim3(256), lds, s, a);
     return hipGetLastError();
   }
+  static hipError_t init(const BatchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((batch_init_kernel<S, B, G, U>), dim3(a.n), dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
   static int resident_per_cu(size_t lds) {
     int b = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_explore_kernel<S, B, G, U>, 256,
@@ -284,6 +288,21 @@ hipError_t batch_launch(uint32_t B, uint32_t G, uint32_t U, const BatchArgs& a, 
                         size_t lds, hipStream_t s) {
 #define GX_BATCH_CASE(BB, GG, UU) \
   if (B == BB && G == GG && U == UU) return BatchKernels<S, BB, GG, UU>::launch(a, grid, lds, s);
+#define GX_BATCH_B(BB) GX_BATCH_CASE(BB, 8, 1) GX_BATCH_CASE(BB, 8, 2) GX_BATCH_CASE(BB, 16, 1) GX_BATCH_CASE(BB, 16, 2)
+#define GX_BATCH_B4(BB) GX_BATCH_B(BB) GX_BATCH_CASE(BB, 4, 1) GX_BATCH_CASE(BB, 4, 2)
+  GX_BATCH_B4(8) GX_BATCH_B4(16) GX_BATCH_B4(32) GX_BATCH_B(64)
+#undef GX_BATCH_B4
+#undef GX_BATCH_B
+#undef GX_BATCH_CASE
+  return hipErrorInvalidValue;
+}
+
+// The initial states alone (the stepped schedule expands the levels with
+// the multi-job step kernel).
+template <int S>
+hipError_t batch_init(uint32_t B, uint32_t G, uint32_t U, const BatchArgs& a, hipStream_t s) {
+#define GX_BATCH_CASE(BB, GG, UU) \
+  if (B == BB && G == GG && U == UU) return BatchKernels<S, BB, GG, UU>::init(a, s);
 #define GX_BATCH_B(BB) GX_BATCH_CASE(BB, 8, 1) GX_BATCH_CASE(BB, 8, 2) GX_BATCH_CASE(BB, 16, 1) GX_BATCH_CASE(BB, 16, 2)
 #define GX_BATCH_B4(BB) GX_BATCH_B(BB) GX_BATCH_CASE(BB, 4, 1) GX_BATCH_CASE(BB, 4, 2)
   GX_BATCH_B4(8) GX_BATCH_B4(16) GX_BATCH_B4(32) GX_BATCH_B(64)

@@ -1,9 +1,10 @@
-// Step kernel of the exploration server: one launch expands the current BFS
-// level of every active job (jobs of one slot width).  Workgroup b takes tile
-// b of the concatenation of all jobs' levels (256 states per tile), finds its
-// job by binary search over the jobs' first tiles, loads that job's network
-// image into LDS and expands the tile with the same per-wavefront routine as
-// the single-exploration kernel.  Jobs join and leave between launches.
+// Step kernel of the exploration server and of the stepped batch schedule:
+// one launch expands the current BFS level of every active job (jobs of one
+// kernel class).  Workgroup b takes tile b of the concatenation of all jobs'
+// levels (256 states per tile), finds its job by binary search over the jobs'
+// first tiles, loads that job's network image into LDS and expands the tile
+// with the same per-wavefront routine as the single-exploration kernel.  Jobs
+// join and leave between launches.
 #pragma once
 
 #include <cstdint>
@@ -23,6 +24,12 @@ struct ServeJob {
   uint64_t dead_cap;
   uint64_t* ctr;        // the job's counters (ctr_at)
   uint64_t tile_begin;  // first tile of this job in the step
+  // a deadlock buffer shared by several jobs: records used (null: the job's
+  // own kCtrDead counter) and, per record, the job's tag (nullable)
+  uint64_t* dead_ctr;
+  uint32_t* dead_tag;
+  uint32_t tag;
+  uint32_t pad;
 };
 
 struct ServeArgs {
@@ -57,10 +64,10 @@ __global__ __launch_bounds__(256) void serve_step_kernel(ServeArgs a) {
   j.frontier_out = jb.frontier_out;
   j.cap_out = jb.cap_out;
   j.dead = jb.dead;
-  j.dead_tag = nullptr;
-  j.tag = 0;
+  j.dead_tag = jb.dead_tag;
+  j.tag = jb.tag;
   j.dead_cap = jb.dead_cap;
-  j.dead_ctr = reinterpret_cast<uint64_t*>(ctr_at(jb.ctr, kCtrDead));
+  j.dead_ctr = jb.dead_ctr ? jb.dead_ctr : reinterpret_cast<uint64_t*>(ctr_at(jb.ctr, kCtrDead));
   j.ctr = jb.ctr;
   j.dtab = nullptr;
   LaneStats st;

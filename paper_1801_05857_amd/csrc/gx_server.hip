@@ -345,6 +345,10 @@ void step_loop(gx_server* s) {
         x.dead_cap = j.t->eb.dead_cap;
         x.ctr = s->d_ctr + kSlotCtrWords * j.slot;
         x.tile_begin = tiles;
+        x.dead_ctr = nullptr;
+        x.dead_tag = nullptr;
+        x.tag = 0;
+        x.pad = 0;
         tiles += (j.n_in + 255) / 256;
         img_max = std::max<uint32_t>(img_max, x.img_words);
         hj.push_back(x);

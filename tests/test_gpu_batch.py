@@ -1,8 +1,9 @@
-"""GPU parity of batched exploration (many networks in one persistent launch
-per kernel class) against the oracle BFS, instance by instance, bit-exact:
-counts, levels, deadlocks and (keep_states) every instance's table contents;
-the benchmarked 1024-network batch against the oracle's results of all its
-instances (tests/golden/batch_1024_s11.txt)."""
+"""GPU parity of batched exploration (many networks explored together: the
+stepped schedule, and the persistent one with and without a hipGraph) against
+the oracle BFS, instance by instance, bit-exact: counts, levels, deadlocks and
+(keep_states) every instance's table contents; the benchmarked 1024-network
+batch against the oracle's results of all its instances
+(tests/golden/batch_1024_s11.txt)."""
 import numpy as np
 import pytest
 
@@ -59,11 +60,14 @@ def _check(res, want, states=False):
             assert np.array_equal(got.states, ref.visited), k
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_matches_oracle(dev, mixed, use_graph):
+SCHEDULES = {"stepped": {}, "persistent": {"persistent": True}, "graph": {"use_graph": True}}
+
+
+@pytest.mark.parametrize("schedule", list(SCHEDULES))
+def test_batch_matches_oracle(dev, mixed, schedule):
     nets, want = mixed
     cap = [max(64, 3 * r.n_states) for r in want]
-    with gx.Batch(nets, cap, use_graph=use_graph, max_hashes=32, keep_states=True) as b:
+    with gx.Batch(nets, cap, max_hashes=32, keep_states=True, **SCHEDULES[schedule]) as b:
         b.run()
         _check(b.results(), want, states=True)
         # a second run resets every table and repeats the batch
@@ -71,13 +75,15 @@ def test_batch_matches_oracle(dev, mixed, use_graph):
         _check(b.results(), want, states=True)
 
 
-def test_benchmarked_batch_matches_oracle(dev):
+@pytest.mark.parametrize("schedule", ["stepped", "graph"])
+def test_benchmarked_batch_matches_oracle(dev, schedule):
     """The 1024-network batch exactly as the benchmark runs it (capacities
-    twice the live-state products, autotuned configurations, hipGraph,
-    16 hash functions): every instance equals the oracle's exploration."""
+    twice the live-state products, autotuned configurations, 16 hash
+    functions; the stepped schedule, and the persistent one from its
+    hipGraph): every instance equals the oracle's exploration."""
     nets, bounds = W.batch_networks(1024, 11)
     want = read_pool("batch_1024_s11.txt")
-    with gx.Batch(nets, [2 * c for c in bounds], use_graph=True, max_hashes=16) as b:
+    with gx.Batch(nets, [2 * c for c in bounds], max_hashes=16, **SCHEDULES[schedule]) as b:
         b.run()
         res = b.results()
     for i, (st, got) in enumerate(res):
@@ -90,15 +96,20 @@ def test_benchmarked_batch_matches_oracle(dev):
         assert oracle.digest(got.deadlocks, got.words_per_state) == ref["dead_digest"], i
 
 
-def test_batch_deeper_than_512_levels(dev):
-    """A single 1500-state cycle: 1500 BFS levels, one queue entry each."""
+@pytest.mark.parametrize("schedule", ["stepped", "persistent"])
+def test_batch_deeper_than_512_levels(dev, schedule):
+    """A single 1500-state cycle: 1500 BFS levels (1500 steps, or one queue
+    entry each)."""
     net = W.independent_cycles((1500,))
     want = oracle.explore(net, want_visited=True)
     assert len(want.levels) == 1500
-    _check(gx.explore_batch([net], [4096], max_hashes=32), [want])
+    _check(gx.explore_batch([net], [4096], max_hashes=32, **SCHEDULES[schedule]), [want])
     # more levels than max_levels: the instance reports GX_ENOMEM
-    res = gx.explore_batch([net], [4096], max_hashes=32, max_levels=1000)
+    res = gx.explore_batch([net], [4096], max_hashes=32, max_levels=1000, **SCHEDULES[schedule])
     assert res[0][0] == gx.GX_ENOMEM
+    # exactly max_levels levels fit
+    _check(gx.explore_batch([net], [4096], max_hashes=32, max_levels=1500,
+                            **SCHEDULES[schedule]), [want])
 
 
 def test_batch_degenerate_networks(dev):
@@ -145,11 +156,12 @@ def test_batch_equals_single_explorations(dev, mixed):
         assert np.array_equal(alone.deadlocks, got.deadlocks)
 
 
-def test_batch_isolates_a_failing_instance(dev):
+@pytest.mark.parametrize("schedule", ["stepped", "persistent"])
+def test_batch_isolates_a_failing_instance(dev, schedule):
     nets = [W.token_ring(6), W.token_ring(8), W.fig1_producer_consumers()]
     want = [oracle.explore(n) for n in nets]
     cap = [3 * want[0].n_states, 64, 64]  # the 34992-state ring gets 64 slots
-    res = gx.explore_batch(nets, cap, max_hashes=4)
+    res = gx.explore_batch(nets, cap, max_hashes=4, **SCHEDULES[schedule])
     assert res[0][0] == gx.GX_OK and res[0][1].n_states == want[0].n_states
     assert res[1][0] == gx.GX_ETABLEFULL and res[1][1] is None
     assert res[2][0] == gx.GX_OK and res[2][1].n_states == 8
