@@ -505,31 +505,45 @@ def run_token_ring(gx, torch, W, sizes=range(2, 17)):
     return rows
 
 
-def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
-    """Batched exploration of n uneven random networks: one persistent launch
-    per kernel class replayed from a hipGraph, against one gx_explore call per
-    instance on pre-created tables (both clear their tables and start over)."""
-    nets, bounds = W.batch_networks(n, seed)
-    caps = [2 * c for c in bounds]  # table slots: load factor at most 0.5
-    t_setup = time.perf_counter()
-    b = gx.Batch(nets, caps, use_graph=True, max_hashes=hashes, bucket_words=B, subgroup=G,
-                 keys_per_subgroup=U)
-    setup_s = time.perf_counter() - t_setup
+def time_batch_runs(b, torch, reps=3):
+    """Median wall time of reps whole runs of a created batch (after one
+    untimed run)."""
     b.run()
     torch.cuda.synchronize()
     runs = []
-    for _ in range(3):
+    for _ in range(reps):
         t0 = time.perf_counter()
         b.run()
         torch.cuda.synchronize()
         runs.append(time.perf_counter() - t0)
+    return sorted(runs)[len(runs) // 2]
+
+
+def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
+    """Batched exploration of n uneven random networks under the stepped
+    schedule (one multi-instance launch per kernel class per BFS level),
+    against the persistent schedule replayed from a hipGraph and against one
+    gx_explore call per instance on pre-created tables (all clear their
+    tables and start over)."""
+    nets, bounds = W.batch_networks(n, seed)
+    caps = [2 * c for c in bounds]  # table slots: load factor at most 0.5
+    t_setup = time.perf_counter()
+    b = gx.Batch(nets, caps, max_hashes=hashes, bucket_words=B, subgroup=G, keys_per_subgroup=U)
+    setup_s = time.perf_counter() - t_setup
+    t_batch = time_batch_runs(b, torch)
     res = b.results()
     cfgs = [b.instance_config(i) for i in range(n)]
     b.close()
+    with gx.Batch(nets, caps, max_hashes=hashes, bucket_words=B, subgroup=G,
+                  keys_per_subgroup=U, use_graph=True) as bg:
+        t_graph = time_batch_runs(bg, torch)
+        res_graph = bg.results()
+    graph_mismatch = sum(1 for (s1, r1), (s2, r2) in zip(res, res_graph)
+                         if s1 != s2 or (r1 is not None and (r1.n_states != r2.n_states or
+                                                             r1.levels.tolist() != r2.levels.tolist())))
     ok = [r for st, r in res if st == gx.GX_OK]
     states = sum(r.n_states for r in ok)
     trans = sum(r.n_transitions for r in ok)
-    t_batch = sorted(runs)[len(runs) // 2]
     algo_bytes = sum(r.n_states * explore_bytes_per_state(r.n_transitions / max(1, r.n_states),
                                                           cfg[0], 4 if r.words_per_state == 3
                                                           else r.words_per_state)
@@ -567,11 +581,14 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
     from collections import Counter
     return {"batched": {
         "workload": f"{n} random networks, 3-10 processes of 4-64 states, reachable sizes "
-                    "log-uniform 1e3-1e7 (live-state products), one persistent launch per "
-                    "kernel class from a hipGraph",
+                    "log-uniform 1e3-1e7 (live-state products), stepped schedule: one "
+                    "multi-instance launch per kernel class per BFS level",
         "instances": n, "ok": len(ok), "states": states, "transitions": trans,
         "seconds": round(t_batch, 4), "states_per_s": round(states / t_batch),
         "roofline": roofline_of(states, algo_bytes, t_batch),
+        "persistent_graph_seconds": round(t_graph, 4),
+        "persistent_graph_states_per_s": round(states / t_graph),
+        "persistent_graph_differing": graph_mismatch,
         "one_launch_per_instance_seconds": round(t_single, 4),
         "one_launch_per_instance_states_per_s": round(single_states / t_single),
         "speedup_vs_one_launch_per_instance": round(t_single / t_batch, 2),
