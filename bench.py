@@ -538,6 +538,30 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
                   keys_per_subgroup=U, use_graph=True) as bg:
         t_graph = time_batch_runs(bg, torch)
         res_graph = bg.results()
+    # the autotuner's decisions behind the per-instance picks (per slot width,
+    # for the combined capacity of its instances), and the same batch at the
+    # fixed default configuration
+    tuner = {}
+    if not (B or G or U):
+        foot = {}
+        for nt, c in zip(nets, caps):
+            w = gx.network_words(nt)
+            S = 4 if w >= 3 else w
+            f = foot.setdefault(S, [w, 0, 0])
+            f[1] += c
+            f[2] += 1
+        for S, (w, total, cnt) in sorted(foot.items()):
+            t = gx.autotune_capacity(w, total)
+            tuner[f"slot_words_{S}"] = {
+                "instances": cnt, "combined_capacity": total, "size_class": t["size_class"],
+                "pick": f"B{t['bucket_words']}-G{t['subgroup']}",
+                "ns_per_key": round(t["ns_per_key"], 4),
+                "ns_per_key_default_B16_G4": round(t["ns_per_key_default"], 4),
+                "ns_per_key_runner_up": round(t["ns_per_key_runner_up"], 4),
+                "margin": round(t["ns_per_key_runner_up"] / t["ns_per_key"] - 1, 4)}
+        with gx.Batch(nets, caps, max_hashes=hashes, bucket_words=16, subgroup=4,
+                      keys_per_subgroup=1) as bf:
+            t_fixed = time_batch_runs(bf, torch)
     graph_mismatch = sum(1 for (s1, r1), (s2, r2) in zip(res, res_graph)
                          if s1 != s2 or (r1 is not None and (r1.n_states != r2.n_states or
                                                              r1.levels.tolist() != r2.levels.tolist())))
@@ -589,6 +613,9 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
         "persistent_graph_seconds": round(t_graph, 4),
         "persistent_graph_states_per_s": round(states / t_graph),
         "persistent_graph_differing": graph_mismatch,
+        "fixed_B16_G4_seconds": round(t_fixed, 4) if tuner else None,
+        "tuned_vs_fixed_B16_G4": round(t_fixed / t_batch, 3) if tuner else None,
+        "autotuner": tuner,
         "one_launch_per_instance_seconds": round(t_single, 4),
         "one_launch_per_instance_states_per_s": round(single_states / t_single),
         "speedup_vs_one_launch_per_instance": round(t_single / t_batch, 2),

@@ -423,7 +423,12 @@ typedef struct {
                                  its two frontier buffers                     */
   uint64_t hash_seed;         /* 0 -> the default seed                         */
   uint32_t max_hashes;        /* H; 0 -> 8                                     */
-  uint32_t bucket_words;      /* 0 -> autotuned per instance, else 8|16|32|64 */
+  uint32_t bucket_words;      /* 0 -> autotuned per instance: the pick of
+                                 gx_autotune_capacity for its words, load 0.5
+                                 and the sum of the capacities of the
+                                 instances of its slot width (their tables
+                                 share the caches while they run together);
+                                 else 8|16|32|64                              */
   uint32_t subgroup;          /* 0 -> autotuned per instance, else 4|8|16
                                  (4 with buckets of at most 32 words; an
                                  explicit 4 caps an autotuned bucket at 32)   */
@@ -479,16 +484,38 @@ gx_status gx_explore_batch(const gx_network* nets, uint32_t n, const gx_batch_op
                            gx_explore_result* outs, gx_status* inst_status);
 
 /*
- * Autotuner: the (bucket words, subgroup, keys per subgroup) with the highest
- * measured find-or-put rate on this device for keys of words_per_state words
- * at the given final load factor (0 < load_factor <= 0.95).  The first call
- * for a (slot words, load) pair times every candidate (B in 8..64, subgroup 4
- * (B <= 32), 8 or 16, 1 or 2 keys per subgroup) on a synthetic stream of
- * 2^26 keys (each distinct key about 8 times), the fastest of three runs
- * each, and returns the first candidate in that order (smaller buckets
- * first) within 2% of the fastest; later calls return the cached choice.
+ * Autotuner: the kernel configuration (bucket words, subgroup; one key in
+ * flight per subgroup, as the exploration kernels keep) for tables of
+ * words_per_state-word states filled to load_factor (0 < load_factor <=
+ * 0.95), per size class of the table's capacity (up to 2^16, 2^20, 2^24
+ * states, and larger: the class decides whether its buckets live in an
+ * XCD's L2, the last-level cache or HBM).  The first call for a (slot words,
+ * load, size class) times every candidate (B in 8..64, subgroup 4 (B <= 32),
+ * 8 or 16) on a stream shaped like an exploration's successor lookups (every
+ * distinct key about 8 times, shuffled; at least 2^25 keys per measurement,
+ * the median of three) into a table at the top of the class, and picks the
+ * fastest, except that the default (B = 16, subgroup 4) is kept when it is
+ * within 3% of the fastest; later calls return the cached choice.
  * Synchronous.
  */
+typedef struct {
+  uint32_t bucket_words, subgroup, keys_per_subgroup;
+  uint32_t candidates;         /* configurations timed                        */
+  double ns_per_key;           /* the pick's time per key                     */
+  double ns_per_key_default;   /* the default's (B = 16, subgroup 4)          */
+  double ns_per_key_runner_up; /* the fastest candidate other than the pick:
+                                  the decision margin is runner_up / pick - 1
+                                  (negative when a near-tie kept the default) */
+  uint64_t table_slots;        /* size of the timed table                     */
+  uint32_t size_class;         /* 0..3                                        */
+  uint32_t pad;
+} gx_tune_info;
+
+gx_status gx_autotune_capacity(uint32_t words_per_state, double load_factor, uint64_t capacity,
+                               gx_tune_info* info);
+
+/* The pick of gx_autotune_capacity for a table of 2^23 / load_factor states
+ * (the size class of 2^23 states at that load). */
 gx_status gx_autotune(uint32_t words_per_state, double load_factor, uint32_t* bucket_words,
                       uint32_t* subgroup, uint32_t* keys_per_subgroup);
 

@@ -32,7 +32,7 @@ EXPORTED = [
     "gx_hash_bucket", "gx_network_words", "gx_network_pack", "gx_explore",
     "gx_explore_result_free", "gx_status_str", "gx_gather_probe",
     "gx_batch_create", "gx_batch_run", "gx_batch_results", "gx_batch_instance_config",
-    "gx_batch_destroy", "gx_explore_batch", "gx_autotune",
+    "gx_batch_destroy", "gx_explore_batch", "gx_autotune", "gx_autotune_capacity",
     "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_get_stats",
     "gx_server_destroy", "gx_network_add_monitor", "gx_monitored_network_free",
     "gx_explore_noalloc",
@@ -123,6 +123,14 @@ class _BatchOpts(ctypes.Structure):
                 ("keep_states", ctypes.c_uint32), ("persistent", ctypes.c_uint32)]
 
 
+class _TuneInfo(ctypes.Structure):
+    _fields_ = [("bucket_words", ctypes.c_uint32), ("subgroup", ctypes.c_uint32),
+                ("keys_per_subgroup", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("ns_per_key", ctypes.c_double), ("ns_per_key_default", ctypes.c_double),
+                ("ns_per_key_runner_up", ctypes.c_double), ("table_slots", ctypes.c_uint64),
+                ("size_class", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
                 ("max_hashes", ctypes.c_uint32), ("load_factor", ctypes.c_double),
@@ -210,6 +218,8 @@ def lib() -> ctypes.CDLL:
         L.gx_batch_destroy.argtypes = [vp]
         L.gx_explore_batch.restype = st
         L.gx_explore_batch.argtypes = [vp, u32, ctypes.POINTER(_BatchOpts), vp, vp]
+        L.gx_autotune_capacity.restype = st
+        L.gx_autotune_capacity.argtypes = [u32, ctypes.c_double, u64, ctypes.POINTER(_TuneInfo)]
         L.gx_autotune.restype = st
         L.gx_autotune.argtypes = [u32, ctypes.c_double, ctypes.POINTER(u32), ctypes.POINTER(u32),
                                   ctypes.POINTER(u32)]
@@ -562,6 +572,15 @@ def autotune(words_per_state: int, load_factor: float = 0.5) -> tuple[int, int, 
     _check(lib().gx_autotune(words_per_state, load_factor, ctypes.byref(b), ctypes.byref(g),
                              ctypes.byref(u)), "gx_autotune")
     return int(b.value), int(g.value), int(u.value)
+
+
+def autotune_capacity(words_per_state: int, capacity: int, load_factor: float = 0.5) -> dict:
+    """gx_autotune_capacity: the pick for tables of `capacity` states, with the
+    timings behind it (ns per key of the pick, the default and the runner-up)."""
+    t = _TuneInfo()
+    _check(lib().gx_autotune_capacity(words_per_state, load_factor, capacity, ctypes.byref(t)),
+           "gx_autotune_capacity")
+    return {n: getattr(t, n) for n, _ in _TuneInfo._fields_ if n != "pad"}
 
 
 class Batch:

@@ -74,13 +74,29 @@ constexpr uint64_t kSpinLimit = 1ull << 23;  // polls of one to two microseconds
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- autotuner
+// Tables are tuned per size class: a table's size decides where most of its
+// buckets live (an XCD's L2, the last-level cache or HBM), and with it the
+// cost of a probe.  Classes: up to 2^16, 2^20, 2^24 slots, and larger.
+constexpr uint32_t kSizeClasses = 4;
+
+uint32_t size_class(uint64_t capacity) {
+  if (capacity <= (uint64_t(1) << 16)) return 0;
+  if (capacity <= (uint64_t(1) << 20)) return 1;
+  if (capacity <= (uint64_t(1) << 24)) return 2;
+  return 3;
+}
+
 struct TuneKey {
   uint32_t S;
   uint32_t load_pct;
-  bool operator<(const TuneKey& o) const { return std::tie(S, load_pct) < std::tie(o.S, o.load_pct); }
+  uint32_t size_class;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(S, load_pct, size_class) < std::tie(o.S, o.load_pct, o.size_class);
+  }
 };
-std::map<TuneKey, std::array<uint32_t, 3>> g_tuned;
+std::map<TuneKey, gx_tune_info> g_tuned;
 std::mutex g_tune_mutex;
+constexpr uint32_t kDefaultB = 16, kDefaultG = 4;  // kept unless beaten by > 3%
 
 __global__ void tune_keys_kernel(uint32_t* keys, uint32_t S, uint64_t n, uint64_t n_distinct,
                                  uint64_t seed) {
@@ -289,6 +305,9 @@ gx_status run_stepped(gx_batch* b, hipStream_t stream) {
   }
   while (true) {
     bool any = false;
+    // the classes' launches of a step run side by side, each on its own
+    // stream, forked from and joined to `stream`
+    if (hipEventRecord(b->ev_fork, stream) != hipSuccess) return GX_EDEVICE;
     for (size_t ci = 0; ci < nk; ++ci) {
       gx_batch::Class& c = b->classes[ci];
       const uint32_t nc = static_cast<uint32_t>(c.members.size());
@@ -327,29 +346,34 @@ gx_status run_stepped(gx_batch* b, hipStream_t stream) {
       sa.n_jobs = n_jobs;
       sa.img = c.img;
       sa.img_stride = c.img_stride;
-      hipError_t e = hipMemcpyAsync(c.d_jobs, c.h_jobs, n_jobs * sizeof(ServeJob),
-                                    hipMemcpyHostToDevice, stream);
+      const hipStream_t cs = c.side;
+      hipError_t e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c.d_jobs, c.h_jobs, n_jobs * sizeof(ServeJob), hipMemcpyHostToDevice,
+                           cs);
       if (e == hipSuccess) {
         const uint32_t grid = static_cast<uint32_t>(tiles);
         switch (c.S) {
-          case 1: e = serve_launch<1>(c.B, c.G, c.U, sa, grid, c.lds, stream); break;
-          case 2: e = serve_launch<2>(c.B, c.G, c.U, sa, grid, c.lds, stream); break;
-          default: e = serve_launch<4>(c.B, c.G, c.U, sa, grid, c.lds, stream); break;
+          case 1: e = serve_launch<1>(c.B, c.G, c.U, sa, grid, c.lds, cs); break;
+          case 2: e = serve_launch<2>(c.B, c.G, c.U, sa, grid, c.lds, cs); break;
+          default: e = serve_launch<4>(c.B, c.G, c.U, sa, grid, c.lds, cs); break;
         }
       }
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(batch_step_summary_kernel, dim3((nc + 255) / 256), dim3(256), 0, stream,
+        hipLaunchKernelGGL(batch_step_summary_kernel, dim3((nc + 255) / 256), dim3(256), 0, cs,
                            c.state, nc, c.d_sum);
         e = hipGetLastError();
       }
       if (e == hipSuccess)
         e = hipMemcpyAsync(c.h_sum, c.d_sum, 2ull * nc * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                           stream);
+                           cs);
+      if (e == hipSuccess) e = hipEventRecord(c.ev_done, cs);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, c.ev_done, 0);
       if (e != hipSuccess) return GX_EDEVICE;
     }
     if (!any) break;
-    // one synchronisation per step: the staged descriptors of this step are
-    // reused only after it
+    // one synchronisation per step (every class joined `stream`): the staged
+    // descriptors of this step are reused only after it
     if (hipStreamSynchronize(stream) != hipSuccess) return GX_EDEVICE;
     for (size_t ci = 0; ci < nk; ++ci) {
       gx_batch::Class& c = b->classes[ci];
@@ -384,97 +408,148 @@ bool valid_pow2(uint32_t x, uint32_t lo, uint32_t hi) {
   return x >= lo && x <= hi && (x & (x - 1)) == 0;
 }
 
+// Times every candidate (B in 8..64 words, subgroup 4 (B <= 32), 8 or 16; one
+// key in flight per subgroup, as the exploration kernels keep) on a stream
+// shaped like an exploration's successor lookups: every distinct key about
+// dup times, shuffled, into a table of the class's size filled to `load` by
+// the end.  One measurement runs the stream r times back to back (clearing
+// the table before each run; the clears are timed alone and subtracted), at
+// least 2^25 keys in all; a candidate's time is the median of three
+// measurements.  The pick is the fastest candidate, unless the default
+// (B = 16, subgroup 4) is within 3% of it: near-ties keep the default, so
+// that run-to-run noise does not flip the choice.
+gx_status tune_class(uint32_t S, double load, uint32_t sc, gx_tune_info* out) {
+  // capacity (states) of the timed table: the top of the class (2^25 for the
+  // open-ended last class)
+  const uint64_t cap_states = sc == 0 ? (uint64_t(1) << 16)
+                              : sc == 1 ? (uint64_t(1) << 20)
+                              : sc == 2 ? (uint64_t(1) << 24)
+                                        : (uint64_t(1) << 25);
+  const uint64_t n_distinct =
+      std::max<uint64_t>(1024, static_cast<uint64_t>(static_cast<double>(cap_states) * load));
+  const uint64_t dup = std::max<uint64_t>(2, std::min<uint64_t>(8, (uint64_t(1) << 26) / n_distinct));
+  const uint64_t n = n_distinct * dup;
+  const uint64_t reps = std::max<uint64_t>(1, (uint64_t(1) << 25) / n);
+  const uint64_t slots = static_cast<uint64_t>(static_cast<double>(n_distinct) / load) + 1;
+  uint32_t* keys = nullptr;
+  uint8_t* status = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (keys) (void)hipFree(keys);
+    if (status) (void)hipFree(status);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&keys, n * S * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&status, n) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return GX_ENOMEM;
+  }
+  hipLaunchKernelGGL(tune_keys_kernel, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0,
+                     nullptr, keys, S, n, n_distinct, 0x5EEDull);
+  // wall time on the device of `reps` runs of (clear, and find-or-put of the
+  // stream unless clear_only)
+  auto time_runs = [&](gx_table* t, bool clear_only, float* ms) -> bool {
+    if (hipEventRecord(e0, nullptr) != hipSuccess) return false;
+    for (uint64_t r = 0; r < reps; ++r) {
+      if (gx_table_clear(t, nullptr) != GX_OK) return false;
+      if (!clear_only && gx_find_or_put(t, keys, n, status, nullptr, nullptr) != GX_OK) return false;
+    }
+    return hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+  };
+  struct Cand {
+    uint32_t B, G;
+    double ns;
+  };
+  std::vector<Cand> cands;
+  gx_status st = GX_OK;
+  for (uint32_t B : {8u, 16u, 32u, 64u}) {
+    if (B < S * 2) continue;
+    for (uint32_t G : {4u, 8u, 16u}) {
+      if (G == 4 && B > 32) continue;
+      gx_table_opts o{0, 64, G, 1, 0};
+      gx_table* t = nullptr;
+      if (gx_table_create(S, B, slots, &o, &t) != GX_OK) {
+        st = GX_ENOMEM;
+        continue;
+      }
+      float clear_ms = 0, ms[3] = {0, 0, 0};
+      bool ok = time_runs(t, false, &ms[0]);  // warm-up
+      ok = ok && time_runs(t, true, &clear_ms);
+      for (int m = 0; m < 3 && ok; ++m) ok = time_runs(t, false, &ms[m]);
+      gx_table_destroy(t);
+      if (!ok) {
+        st = GX_EDEVICE;
+        continue;
+      }
+      std::sort(ms, ms + 3);
+      const double work = std::max(1e-6, static_cast<double>(ms[1] - clear_ms));
+      cands.push_back({B, G, work * 1e6 / static_cast<double>(reps * n)});
+    }
+  }
+  cleanup();
+  if (cands.empty()) return st == GX_OK ? GX_EDEVICE : st;
+  size_t best = 0, def = cands.size();
+  for (size_t k = 0; k < cands.size(); ++k) {
+    if (cands[k].ns < cands[best].ns) best = k;
+    if (cands[k].B == kDefaultB && cands[k].G == kDefaultG) def = k;
+  }
+  size_t pick = best;
+  if (def < cands.size() && cands[def].ns <= cands[best].ns * 1.03) pick = def;
+  double runner = 0;
+  for (size_t k = 0; k < cands.size(); ++k)
+    if (k != pick && (runner == 0 || cands[k].ns < runner)) runner = cands[k].ns;
+  out->bucket_words = cands[pick].B;
+  out->subgroup = cands[pick].G;
+  out->keys_per_subgroup = 1;
+  out->candidates = static_cast<uint32_t>(cands.size());
+  out->ns_per_key = cands[pick].ns;
+  out->ns_per_key_default = def < cands.size() ? cands[def].ns : 0.0;
+  out->ns_per_key_runner_up = runner;
+  out->table_slots = slots;
+  out->size_class = sc;
+  out->pad = 0;
+  return GX_OK;
+}
+
 }  // namespace
 }  // namespace gx
 
 // ====================================================================== ABI
 extern "C" {
 
+gx_status gx_autotune_capacity(uint32_t w, double load, uint64_t capacity, gx_tune_info* info) {
+  if (w < 1 || w > 4 || !(load > 0.0) || load > 0.95 || capacity == 0 || !info)
+    return GX_EINVAL;
+  const uint32_t S = gx::slot_words(w);
+  const gx::TuneKey key{S, static_cast<uint32_t>(load * 100.0 + 0.5), gx::size_class(capacity)};
+  std::lock_guard<std::mutex> lock(gx::g_tune_mutex);
+  auto it = gx::g_tuned.find(key);
+  if (it == gx::g_tuned.end()) {
+    gx_tune_info t{};
+    const gx_status st = gx::tune_class(S, load, key.size_class, &t);
+    if (st != GX_OK) return st;
+    it = gx::g_tuned.emplace(key, t).first;
+  }
+  *info = it->second;
+  return GX_OK;
+}
+
 gx_status gx_autotune(uint32_t w, double load, uint32_t* B_out, uint32_t* G_out,
                       uint32_t* U_out) {
   if (w < 1 || w > 4 || !(load > 0.0) || load > 0.95 || !B_out || !G_out || !U_out)
     return GX_EINVAL;
-  const uint32_t S = gx::slot_words(w);
-  const gx::TuneKey key{S, static_cast<uint32_t>(load * 100.0 + 0.5)};
-  std::lock_guard<std::mutex> lock(gx::g_tune_mutex);
-  auto it = gx::g_tuned.find(key);
-  if (it == gx::g_tuned.end()) {
-    // measure every candidate on a synthetic stream of 2^26 keys, each
-    // distinct key about 8 times (most lookups find their key, as the
-    // successor lookups of an exploration do), into a table sized for the
-    // requested load factor (150-900 MB: beyond the L2 and the last-level
-    // cache, as the tables it is tuned for are); shorter streams end before
-    // the kernel reaches its steady rate
-    const uint64_t n = 1u << 26, n_distinct = n / 8;
-    uint32_t* keys = nullptr;
-    uint8_t* status = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipMalloc(&keys, n * S * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&status, n) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-        hipEventCreate(&e1) != hipSuccess) {
-      (void)hipGetLastError();
-      if (keys) (void)hipFree(keys);
-      if (status) (void)hipFree(status);
-      return GX_ENOMEM;
-    }
-    hipLaunchKernelGGL(gx::tune_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, nullptr, keys,
-                       S, n, n_distinct, 0x5EEDull);
-    float best = 1e30f;
-    std::vector<std::pair<float, std::array<uint32_t, 3>>> timed;  // in candidate order
-    gx_status st = GX_OK;
-    for (uint32_t B : {8u, 16u, 32u, 64u}) {
-      if (B < S * 2) continue;
-      for (uint32_t G : {4u, 8u, 16u}) {
-        if (G == 4 && B > 32) continue;
-        for (uint32_t U : {1u, 2u}) {
-          gx_table_opts o{0, 64, G, U, 0};
-          gx_table* t = nullptr;
-          if (gx_table_create(S == 4 ? 4 : S, B, static_cast<uint64_t>(n_distinct / load) + 1, &o,
-                              &t) != GX_OK) {
-            st = GX_ENOMEM;
-            continue;
-          }
-          // warm-up, then the fastest of three timed insertions into the
-          // cleared table
-          (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
-          float fastest = 1e30f;
-          for (int rep = 0; rep < 3; ++rep) {
-            float ms = 0;
-            (void)gx_table_clear(t, nullptr);
-            (void)hipEventRecord(e0, nullptr);
-            (void)gx_find_or_put(t, keys, n, status, nullptr, nullptr);
-            (void)hipEventRecord(e1, nullptr);
-            if (hipEventSynchronize(e1) == hipSuccess &&
-                hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-              fastest = std::min(fastest, ms);
-          }
-          best = std::min(best, fastest);
-          timed.push_back({fastest, {B, G, U}});
-          gx_table_destroy(t);
-        }
-      }
-    }
-    (void)hipFree(keys);
-    (void)hipFree(status);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (best >= 1e30f) return st == GX_OK ? GX_EDEVICE : st;
-    // the first candidate within 2% of the fastest: candidates are ordered by
-    // bucket size, then subgroup, then keys in flight, so near-ties go to the
-    // smaller bucket (fewer bytes per probe; in explorations with 4-word
-    // slots 16-word buckets beat 32-word ones that tie on this stream)
-    std::array<uint32_t, 3> pick{32, 8, 1};
-    for (const auto& c : timed) {
-      if (c.first <= best * 1.02f) {
-        pick = c.second;
-        break;
-      }
-    }
-    it = gx::g_tuned.emplace(key, pick).first;
-  }
-  *B_out = it->second[0];
-  *G_out = it->second[1];
-  *U_out = it->second[2];
+  // the size class of a table for 2^23 states at this load
+  gx_tune_info t{};
+  const gx_status st = gx_autotune_capacity(
+      w, load, static_cast<uint64_t>(static_cast<double>(uint64_t(1) << 23) / load) + 1, &t);
+  if (st != GX_OK) return st;
+  *B_out = t.bucket_words;
+  *G_out = t.subgroup;
+  *U_out = t.keys_per_subgroup;
   return GX_OK;
 }
 
@@ -520,23 +595,28 @@ gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opt
   b->tab_off.resize(n);
   b->tab_words.resize(n);
   b->keep_states = opts->keep_states != 0;
-  // per-instance kernel configuration: explicit, else autotuned for the
-  // instance's slot width at the load factor its capacity is declared for
+  // per-instance kernel configuration: explicit, else the autotuner's pick
+  // for the instance's slot width and the combined capacity of the batch's
+  // instances of that width: they run side by side, so their tables share
+  // the caches, and the footprint that decides a probe's cost is theirs
+  // together (tuned for its own size alone, a small instance's pick assumes
+  // a table resident in an XCD's L2)
+  uint64_t footprint[5] = {0, 0, 0, 0, 0};
+  for (uint32_t i = 0; i < n; ++i) footprint[gx::slot_words(words[i])] += opts->capacity[i];
   for (uint32_t i = 0; i < n; ++i) {
     uint32_t B = opts->bucket_words, G = opts->subgroup, U = opts->keys_per_subgroup;
     if (!B || !G || !U) {
-      uint32_t tb = 32, tg = 8, tu = 1;
-      const gx_status s = gx_autotune(words[i], 0.5, &tb, &tg, &tu);
+      gx_tune_info ti{};
+      const gx_status s =
+          gx_autotune_capacity(words[i], 0.5, footprint[gx::slot_words(words[i])], &ti);
       if (s != GX_OK) {
         gx::free_batch(b);
         return s;
       }
-      B = B ? B : tb;
-      G = G ? G : tg;
-      // one key in flight per subgroup unless asked: the autotuner times the
-      // isolated find-or-put, where more keys in flight pay off, but in the
-      // exploration kernels they cost a wave per SIMD of occupancy
-      (void)tu;
+      B = B ? B : ti.bucket_words;
+      G = G ? G : ti.subgroup;
+      // one key in flight per subgroup unless asked: more keys in flight cost
+      // the exploration kernels a wave per SIMD of occupancy
       U = U ? U : 1;
       gx::fit_subgroup(&B, &G, opts->bucket_words != 0);
     }

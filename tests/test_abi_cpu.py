@@ -182,6 +182,11 @@ def test_batch_arguments_rejected_before_device_work(lib):
     b = ctypes.c_uint32()
     assert lib.gx_autotune(0, 0.5, ctypes.byref(b), ctypes.byref(b), ctypes.byref(b)) == gx.GX_EINVAL
     assert lib.gx_autotune(2, 0.0, ctypes.byref(b), ctypes.byref(b), ctypes.byref(b)) == gx.GX_EINVAL
+    t = gx._TuneInfo()
+    assert lib.gx_autotune_capacity(0, 0.5, 1024, ctypes.byref(t)) == gx.GX_EINVAL
+    assert lib.gx_autotune_capacity(2, 0.96, 1024, ctypes.byref(t)) == gx.GX_EINVAL
+    assert lib.gx_autotune_capacity(2, 0.5, 0, ctypes.byref(t)) == gx.GX_EINVAL
+    assert lib.gx_autotune_capacity(2, 0.5, 1024, None) == gx.GX_EINVAL
 
 
 def test_server_arguments_rejected(lib):

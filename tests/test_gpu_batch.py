@@ -180,3 +180,47 @@ def test_autotune_returns_a_valid_configuration(dev):
         assert B in (8, 16, 32, 64) and G in (4, 8, 16) and U in (1, 2)
         assert G != 4 or B <= 32  # a 4-lane subgroup covers at most 32 words
         assert gx.autotune(w, 0.5) == (B, G, U)  # cached
+
+
+def _size_class(cap):
+    return 0 if cap <= 1 << 16 else 1 if cap <= 1 << 20 else 2 if cap <= 1 << 24 else 3
+
+
+def test_autotune_per_size_class(dev):
+    """Picks per (words, table size class), cached, with the timings behind
+    them; the default B16-G4 is kept unless beaten by more than 3%."""
+    for w in (1, 2):
+        for cap in (1 << 12, 1 << 18, 1 << 22):
+            t = gx.autotune_capacity(w, cap)
+            assert t["size_class"] == _size_class(cap)
+            assert t["keys_per_subgroup"] == 1 and t["candidates"] >= 8
+            assert t["bucket_words"] in (8, 16, 32, 64) and t["subgroup"] in (4, 8, 16)
+            assert t["ns_per_key"] > 0 and t["ns_per_key_default"] > 0
+            assert t["ns_per_key_runner_up"] > 0
+            if (t["bucket_words"], t["subgroup"]) != (16, 4):
+                assert t["ns_per_key"] * 1.03 < t["ns_per_key_default"]
+            else:
+                assert t["ns_per_key"] == t["ns_per_key_default"]
+            assert gx.autotune_capacity(w, cap) == t  # cached
+            # any capacity of the same class gets the same pick
+            assert gx.autotune_capacity(w, cap - 1) == t
+
+
+def test_batch_tunes_for_the_combined_footprint(dev):
+    """An instance's autotuned configuration is the pick for its words and the
+    combined capacity of the batch's instances of its slot width."""
+    # 810, 34992, 1299078 and 8 reachable states (one-, one-, two- and
+    # one-word vectors)
+    nets = [W.token_ring(5), W.token_ring(8), W.token_ring(11), W.fig1_producer_consumers()]
+    caps = [1 << 11, 1 << 17, 1 << 22, (1 << 24) + 1]
+    words = [gx.network_words(nt) for nt in nets]
+    assert words == [1, 1, 2, 1]
+    total = {}
+    for w, c in zip(words, caps):
+        total[w] = total.get(w, 0) + c
+    with gx.Batch(nets, caps, max_hashes=32) as b:
+        for i, w in enumerate(words):
+            t = gx.autotune_capacity(w, total[w])
+            assert b.instance_config(i) == (t["bucket_words"], t["subgroup"], 1)
+        b.run()
+        _check(b.results(), [oracle.explore(n) for n in nets])
