@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="served exploration: Poisson request streams at 0.1-1.2x saturation")
     ap.add_argument("--serve-n", type=int, default=1000, help="requests per rate")
+    ap.add_argument("--serve-rates", default="0.1,0.25,0.5,0.75,1.0,1.2",
+                    help="Poisson rates as multiples of saturation (empty: saturation only)")
     ap.add_argument("--tiny", action="store_true",
                     help="only the tiny configuration")
     ap.add_argument("--explore-large", action="store_true",
@@ -808,7 +810,8 @@ def main():
                                    G=args.batch_subgroup, U=args.batch_kps)), flush=True)
         return
     if args.serve:
-        print(json.dumps(run_serve(gx, torch, W, args.serve_n)), flush=True)
+        rates = tuple(float(x) for x in args.serve_rates.split(",") if x.strip())
+        print(json.dumps(run_serve(gx, torch, W, args.serve_n, rates=rates)), flush=True)
         return
     if args.tiny:
         print(json.dumps(run_tiny(gx, torch, W)), flush=True)
