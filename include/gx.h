@@ -324,7 +324,10 @@ typedef struct {
  * slices sized so that neither the next frontier nor the successor buffer
  * can overflow even if every successor were new; each slice is one
  * successor-generation launch followed by one find-or-put-and-append launch
- * on opts->hip_stream.
+ * on opts->hip_stream.  The network image (the transition tables of every
+ * process and rule, about one word per local state and transition) is read
+ * from LDS when it fits 11776 words (46 KiB), else from global memory (up to
+ * 2^26 words; such networks skip the small-level path).
  *
  * Safety check (Sec. 3: the negation of a safety property is an automaton
  * added to the network as one more process): with opts->monitor_bad set, a
@@ -337,7 +340,7 @@ typedef struct {
  *
  * Synchronous: returns when the exploration ends.
  * Errors: GX_EINVAL (invalid network, word count mismatch, non-empty table,
- * network image too large for the kernel's LDS, monitor_proc out of range),
+ * network image above 2^26 words, monitor_proc out of range),
  * GX_ETABLEFULL (a state
  * exhausted every hash function; exploration stops, no result), GX_ENOMEM
  * (frontier or deadlock buffer too small, or allocation failure).
@@ -385,8 +388,9 @@ typedef struct {
  * table keeps what was stored).  Every call on a GPU uses that GPU's one
  * array: calls that overlap on one GPU (two host threads, or two streams)
  * race and must be serialised by the caller.  Synchronous.
- * Errors: as gx_explore, plus GX_EINVAL for a monitor, null arrays or a
- * table on another device.
+ * Errors: as gx_explore, plus GX_EINVAL for a monitor, null arrays, a
+ * table on another device or a network image beyond the 46 KiB the control
+ * block holds.
  */
 gx_status gx_explore_noalloc(const gx_network* net, gx_table* table, const gx_explore_opts* opts,
                              uint64_t* level_counts, uint32_t max_levels, uint32_t* deadlocks,
@@ -454,8 +458,10 @@ typedef struct {
                                  graph; 0 (and use_graph 0): stepped          */
 } gx_batch_opts;
 
-/* Compile every network (argument errors before device work), choose each
- * instance's kernel configuration, allocate and upload.  Synchronous. */
+/* Compile every network (argument errors before device work, GX_EINVAL also
+ * for a network image beyond the 46 KiB of LDS the batch kernels keep it
+ * in), choose each instance's kernel configuration, allocate and upload.
+ * Synchronous. */
 gx_status gx_batch_create(const gx_network* nets, uint32_t n, const gx_batch_opts* opts,
                           gx_batch** out);
 
@@ -568,7 +574,8 @@ typedef struct {
 gx_status gx_server_create(const gx_server_opts* opts, gx_server** out);
 
 /* Queue a request; the network is compiled and copied before return.
- * Errors: GX_EINVAL (invalid network, bound 0). */
+ * Errors: GX_EINVAL (invalid network, a network image beyond the 46 KiB of
+ * LDS the step kernel keeps it in, bound 0). */
 gx_status gx_server_submit(gx_server* server, const gx_network* net, uint64_t declared_states,
                            uint64_t* request_id);
 

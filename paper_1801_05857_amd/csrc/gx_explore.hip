@@ -69,6 +69,9 @@ namespace gx {
 //                   target of local state l, entry l+1 one past its last
 //   target arrays:  target local states
 constexpr uint32_t kMaxSuccPerState = 1u << 20;
+// Largest image of any kernel: one that exceeds kImgMaxWords (the LDS budget)
+// is read from global memory by the exploration's generation kernel.
+constexpr uint32_t kImgGlobalMaxWords = 1u << 26;
 
 struct NetImage {
   std::vector<uint32_t> img;
@@ -86,7 +89,8 @@ uint32_t field_bits(uint32_t n) {
   return b;
 }
 
-gx_status compile_network(const gx_network* net, NetImage* out) {
+gx_status compile_network(const gx_network* net, NetImage* out,
+                          uint32_t max_words = kImgGlobalMaxWords) {
   if (!net || net->n_procs == 0 || !net->procs) return GX_EINVAL;
   if (net->n_rules && !net->rules) return GX_EINVAL;
   const uint32_t P = net->n_procs, R = net->n_rules, NL = net->n_labels;
@@ -143,7 +147,7 @@ gx_status compile_network(const gx_network* net, NetImage* out) {
       img.push_back(0);  // patched below
     }
   }
-  auto too_big = [&]() { return img.size() > kImgMaxWords; };
+  auto too_big = [&]() { return img.size() > max_words; };
   // CSR of targets selected by `keep` for process p: offsets then targets
   auto emit_csr = [&](uint32_t p, auto keep, uint64_t* max_deg) -> uint32_t {
     const gx_lts& l = net->procs[p];
@@ -202,7 +206,8 @@ gx_status compile_network_image(const gx_network* net, std::vector<uint32_t>* im
                                 uint32_t* words, std::vector<uint32_t>* packed_initial,
                                 uint64_t* max_succ) {
   NetImage ni;
-  const gx_status s = compile_network(net, &ni);
+  // batches and the server keep every image in LDS
+  const gx_status s = compile_network(net, &ni, kImgMaxWords);
   if (s != GX_OK) return s;
   packed_initial->assign(4, 0);
   pack_host(ni, ni.initial.data(), packed_initial->data());
@@ -464,7 +469,8 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
                               gx_explore_buffers& eb, gx::FixedOut* fixed,
                               gx_explore_result* out) {
   gx::NetImage ni;
-  gx_status s = gx::compile_network(net, &ni);
+  // (with preallocated buffers the image must fit the control block)
+  gx_status s = gx::compile_network(net, &ni, fixed ? gx::kImgMaxWords : gx::kImgGlobalMaxWords);
   if (s != GX_OK) return s;
   if (ni.words != t->w) return GX_EINVAL;
   const bool monitor = opts && opts->monitor_bad;
@@ -490,13 +496,32 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
 
   // resident buffers of the table (allocated on first use, grow-only)
   const uint32_t img_words = static_cast<uint32_t>(ni.img.size());
-  const uint32_t img_stride = (img_words + 3) & ~3u;
+  // an image beyond the LDS budget stays in global memory (a buffer of its
+  // own), read there by the generation kernel; such networks take no
+  // small-level path (its kernels keep the image in LDS)
+  const bool global_img = img_words > gx::kImgMaxWords;
+  const uint32_t img_stride = global_img ? 0u : (img_words + 3) & ~3u;
   // the control block: the level's counters, what a small-level launch
   // reports (read back together), the initial state's slot, the image
   constexpr size_t kCtrWords = gx::kCtrWords;
   constexpr size_t kBlockWords = gx::kBlockWords;
   constexpr size_t kControlBytes = gx::kControlBytes;
-  if (img_stride > gx::kImgMaxWords) return GX_EINVAL;
+  if (global_img) {
+    if (fixed) return GX_EINVAL;
+    if (eb.img_global_cap < img_words) {
+      if (eb.img_global) (void)hipFree(eb.img_global);
+      eb.img_global = nullptr;
+      eb.img_global_cap = 0;
+      if (hipMalloc(&eb.img_global, img_words * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GX_ENOMEM;
+      }
+      eb.img_global_cap = img_words;
+    }
+    if (hipMemcpyAsync(eb.img_global, ni.img.data(), img_words * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, stream) != hipSuccess)
+      return GX_EDEVICE;
+  }
   if (!eb.ctr && (hipMalloc(&eb.ctr, kControlBytes) != hipSuccess ||
                   hipHostMalloc(&eb.ctr_host, kControlBytes) != hipSuccess ||
                   hipMalloc(&eb.status, 8) != hipSuccess)) {
@@ -515,7 +540,7 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
   // duplicate filter, whose per-level work stays on the host path.
   const bool dedup = opts && opts->local_dedup;
   uint64_t small_limit = 0;
-  if (!monitor && !dedup) {
+  if (!monitor && !dedup && !global_img) {
     if ((s = grow_buf(&eb.succ, &eb.succ_cap, 1, 0, ~0ull)) != GX_OK) return s;
     const uint64_t room = std::min<uint64_t>(
         std::min<uint64_t>(eb.f_cap[0], eb.f_cap[1]),
@@ -537,8 +562,9 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
     std::memset(ctr_raw, 0, kBlockWords * sizeof(uint64_t));
     uint32_t* hkey = reinterpret_cast<uint32_t*>(ctr_raw + kBlockWords);
     std::memcpy(hkey, init, 4 * sizeof(uint32_t));
-    std::memcpy(hkey + 4, ni.img.data(), img_words * sizeof(uint32_t));
-    const size_t up = kBlockWords * sizeof(uint64_t) + (4 + img_words) * sizeof(uint32_t);
+    const uint32_t lds_img = global_img ? 0u : img_words;
+    std::memcpy(hkey + 4, ni.img.data(), lds_img * sizeof(uint32_t));
+    const size_t up = kBlockWords * sizeof(uint64_t) + (4 + lds_img) * sizeof(uint32_t);
     if (hipMemcpyAsync(eb.ctr, ctr_raw, up, hipMemcpyHostToDevice, stream) != hipSuccess)
       return GX_EDEVICE;
   }
@@ -602,9 +628,10 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
   }
 
   gx::GenArgs g;
-  g.img = eb.img;
+  g.img = global_img ? eb.img_global : eb.img;
   g.img_words = img_words;
-  g.img_stride = img_stride;
+  g.img_stride = img_stride;  // LDS words of the image (0: read from global memory)
+  g.global_img = global_img ? 1u : 0u;
   g.ctr = eb.ctr;
   g.dedup = opts && opts->local_dedup ? 1u : 0u;
   gx::AppendArgs ap;

@@ -425,9 +425,10 @@ __device__ inline void expand_wave(const WaveJob& j, uint32_t* stage, LaneStats&
 // successor generation.
 
 struct GenArgs {
-  const uint32_t* img;
+  const uint32_t* img;  // global memory (copied to LDS unless global_img)
   uint32_t img_words;
-  uint32_t img_stride;  // img_words rounded up to 4
+  uint32_t img_stride;  // LDS words of the image: img_words rounded up to 4, 0 with global_img
+  uint32_t global_img;  // the image is read from global memory (too large for LDS)
   const uint32_t* frontier_in;
   uint64_t n_in;
   uint32_t* succ;       // successor keys, S words each
@@ -513,17 +514,25 @@ __device__ inline void gen_wave_filtered(const GenArgs& a, const uint32_t* img, 
 
 // kFilter (a.dedup set): the chunked path with the duplicate filter, built as
 // its own kernel so its registers do not lower the plain path's occupancy.
-template <int S, bool kFilter>
+// kGlobalImg (a.global_img set): the image is read where it is, in global
+// memory (through the caches), for networks whose image exceeds the LDS
+// budget; a kernel of its own, so the LDS path keeps its LDS loads.
+template <int S, bool kFilter, bool kGlobalImg>
 __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   extern __shared__ uint32_t smem[];
   __shared__ uint32_t wave_total[4];
   __shared__ unsigned long long group_base;
-  uint32_t* img = smem;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *ctr_at(a.ctr, a.succ_ctr == kCtrSucc ? kCtrSuccAlt : kCtrSucc) = 0;
     if (a.reset_tail) *ctr_at(a.ctr, kCtrTail) = 0;
   }
-  for (uint32_t k = threadIdx.x; k < a.img_words; k += 256) img[k] = a.img[k];
+  const uint32_t* img;
+  if constexpr (kGlobalImg) {
+    img = a.img;
+  } else {
+    for (uint32_t k = threadIdx.x; k < a.img_words; k += 256) smem[k] = a.img[k];
+    img = smem;
+  }
   __syncthreads();
   const int wave = static_cast<int>(threadIdx.x >> 6);
   const uint64_t first = static_cast<uint64_t>(blockIdx.x) * 256 + (threadIdx.x & ~63u);
@@ -656,20 +665,26 @@ hipError_t launch_append(const AppendArgs& a, uint32_t cus, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int S>
-hipError_t launch_gen(const GenArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
-  const void* k = a.dedup ? reinterpret_cast<const void*>(&gen_level_kernel<S, true>)
-                         : reinterpret_cast<const void*>(&gen_level_kernel<S, false>);
+template <int S, bool kFilter, bool kGlobalImg>
+hipError_t launch_gen_k(const GenArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
   if (lds > 65536) {  // more than the default per-workgroup LDS: ask for it
-    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             static_cast<int>(lds));
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&gen_level_kernel<S, kFilter, kGlobalImg>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
-  if (a.dedup)
-    hipLaunchKernelGGL((gen_level_kernel<S, true>), dim3(grid), dim3(256), lds, s, a);
-  else
-    hipLaunchKernelGGL((gen_level_kernel<S, false>), dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((gen_level_kernel<S, kFilter, kGlobalImg>), dim3(grid), dim3(256), lds, s,
+                     a);
   return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_gen(const GenArgs& a, uint32_t grid, size_t lds, hipStream_t s) {
+  if (a.global_img)
+    return a.dedup ? launch_gen_k<S, true, true>(a, grid, lds, s)
+                   : launch_gen_k<S, false, true>(a, grid, lds, s);
+  return a.dedup ? launch_gen_k<S, true, false>(a, grid, lds, s)
+                 : launch_gen_k<S, false, false>(a, grid, lds, s);
 }
 
 template <int S, int B, int G>

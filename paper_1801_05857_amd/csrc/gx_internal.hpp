@@ -14,6 +14,8 @@
 struct gx_explore_buffers {
   uint32_t* img = nullptr;  // network image (in the control block, see ctr)
   uint64_t img_cap = 0;     // words
+  uint32_t* img_global = nullptr;  // an image too large for LDS (own allocation)
+  uint64_t img_global_cap = 0;     // words
   uint32_t* f[2] = {nullptr, nullptr};
   uint64_t f_cap[2] = {0, 0};  // states
   uint32_t* dead = nullptr;

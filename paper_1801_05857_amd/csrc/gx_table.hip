@@ -126,7 +126,7 @@ void free_table(gx_table* t) {
                   static_cast<void*>(e.dead), static_cast<void*>(e.succ),
                   static_cast<void*>(e.ctr), static_cast<void*>(e.status),
                   static_cast<void*>(e.mon), static_cast<void*>(e.viol),
-                  static_cast<void*>(e.viol_ctr)})
+                  static_cast<void*>(e.viol_ctr), static_cast<void*>(e.img_global)})
     if (p) (void)hipFree(p);
   if (e.ctr_host) (void)hipHostFree(e.ctr_host);
   delete t;

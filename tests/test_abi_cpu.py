@@ -218,3 +218,14 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "--gpus must be 1" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_networks_with_images_beyond_lds_compile(lib):
+    """A network whose compiled image exceeds the 46 KiB LDS budget still
+    compiles for gx_explore (its image is then read from global memory):
+    its words and packing are available on the host."""
+    import workloads as W
+    net = W.random_lts(21, 4, 4096, 12, 3, 32, 0.25, 0.1)  # 4 x 4097 offsets alone
+    assert gx.network_words(net) == 2
+    packed = gx.network_pack(net, np.zeros((1, 4), dtype=np.uint32))
+    assert packed.shape == (1, 2) and not packed.any()
