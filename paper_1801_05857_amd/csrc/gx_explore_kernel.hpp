@@ -106,13 +106,17 @@ __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) 
 // per lane would touch a cache line per lane.  kWindow: runs whose numbers
 // all lie below lo are counted with one wavefront sum instead of walked, and
 // the walk stops at hi (used to expand a wavefront's successors chunk by
-// chunk); without it the window must be [0, total).  Must be reached by the
-// whole wavefront; a lane without a state passes has = false.
+// chunk); without it the window must be [0, total), or [0, hi) with hi at
+// least the total.  Must be reached by the whole wavefront; a lane without a
+// state passes has = false.  Optional outputs: *total, the wavefront's
+// successors (without the window: all of them), and *mine, this lane's.
 template <int S, bool kWindow>
 __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t (&sw)[S],
-                                            bool has, uint32_t* out, uint32_t lo, uint32_t hi) {
+                                            bool has, uint32_t* out, uint32_t lo, uint32_t hi,
+                                            uint32_t* total = nullptr, uint32_t* mine = nullptr) {
   const uint32_t P = img[0], R = img[1];
   uint32_t cur = 0;  // successors the wavefront has numbered (the same in every lane)
+  uint32_t own = 0;  // this lane's
   auto put = [&](bool act, const uint32_t (&succ)[S]) {
     const uint64_t m = __ballot(act);
     const uint32_t k = cur + __builtin_amdgcn_mbcnt_hi(
@@ -120,6 +124,7 @@ __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t 
                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
     if (act && k >= lo && k < hi) store_slot<S>(out + static_cast<uint64_t>(k - lo) * S, succ);
     cur += static_cast<uint32_t>(__popcll(m));
+    if (mine) own += act ? 1u : 0u;
   };
   // true when all n successors per lane still to come lie below the window:
   // then they are only counted
@@ -208,6 +213,8 @@ __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t 
       put(act, succ);
     }
   }
+  if (total) *total = cur;
+  if (mine) *mine = own;
 }
 
 // Exclusive prefix sum over the 64 lanes of a wavefront; *total receives the

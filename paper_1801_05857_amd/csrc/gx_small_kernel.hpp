@@ -285,6 +285,8 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
   uint32_t* stage = set + n_set * S + wave * kChunk * S;
   uint32_t* log = a.succ;
   const uint64_t set_cap = static_cast<uint64_t>(n_set) / 4 * 3;
+  // a wavefront's 64 states have at most 64 * max_succ successors
+  const bool one_chunk = static_cast<uint64_t>(a.max_succ) * 64 <= kChunk;
   for (uint32_t k = tid; k < a.img_words; k += kSmallThreads) img[k] = a.img[k];
   for (uint32_t k = tid; k < n_set * S; k += kSmallThreads) set[k] = kEmpty;
   __syncthreads();
@@ -319,19 +321,44 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
 #pragma unroll
       for (int x = 0; x < S; ++x) sw[x] = 0;
       if (has) load_slot<S>(log + static_cast<uint64_t>(ls + i) * S, sw);
-      const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
-      if (has && c == 0) {
-        const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
-        if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
-        atomicAdd(&sh_dead, 1u);
-      }
       uint32_t total = 0;
-      (void)wave_exclusive_scan(c, &total);
+      bool staged = false;  // the wavefront's successors are in its stage already
+      if (one_chunk) {
+        // every state's successors fit one chunk: emitted at once, counted
+        // on the way (this lane's for the deadlock test)
+        uint32_t c = 0;
+        emit_window<S, false>(img, sw, has, stage, 0, kChunk, &total, &c);
+        if (has && c == 0) {
+          const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
+          if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
+          atomicAdd(&sh_dead, 1u);
+        }
+        staged = true;
+      } else {
+        const uint32_t c = has ? count_successors<S>(img, sw) : 0u;
+        if (has && c == 0) {
+          const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
+          if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
+          atomicAdd(&sh_dead, 1u);
+        }
+        (void)wave_exclusive_scan(c, &total);
+      }
       if (lane == 0 && total) atomicAdd(&sh_trans, static_cast<unsigned long long>(total));
       for (uint32_t lo = 0; lo < total; lo += kChunk) {
         const uint32_t hi = min(total, lo + kChunk);
-        emit_window<S, true>(img, sw, has, stage, lo, hi);
+        // (a wavefront whose successors fit one chunk walks them without the
+        // window's per-run wavefront sums)
+        if (!staged) {
+          if (lo == 0 && hi == total)
+            emit_window<S, false>(img, sw, has, stage, 0, total);
+          else
+            emit_window<S, true>(img, sw, has, stage, lo, hi);
+        }
         wave_lds_sync();
+        // NEW states of the chunk are compacted in place at the front of the
+        // stage (each round reads its keys before any is rewritten), then
+        // logged with one reservation
+        uint32_t n_new = 0;
         for (uint32_t r0 = 0; r0 < hi - lo; r0 += 64) {
           const uint32_t idx = r0 + lane;
           const bool act = idx < hi - lo;
@@ -340,13 +367,21 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
           for (int x = 0; x < S; ++x) key[x] = act ? stage[idx * S + x] : 0u;
           const bool fresh = lds_set_insert<S>(set, a.set_mask, key, act);
           const uint64_t m = __ballot(fresh);
-          if (m) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&sh_log_n, static_cast<uint32_t>(__popcll(m)));
-            base = __shfl(base, 0, 64);
-            if (fresh)
-              store_slot<S>(log + (base + __popcll(m & ((1ull << lane) - 1ull))) * S, key);
+          wave_lds_sync();  // every lane's key of this round is read before any write
+          if (fresh) {
+            const uint32_t pos = n_new + static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+#pragma unroll
+            for (int x = 0; x < S; ++x) stage[pos * S + x] = key[x];
           }
+          n_new += static_cast<uint32_t>(__popcll(m));
+        }
+        wave_lds_sync();
+        if (n_new) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&sh_log_n, n_new);
+          base = __shfl(base, 0, 64);
+          for (uint32_t k = lane; k < n_new * S; k += 64)
+            log[static_cast<uint64_t>(base) * S + k] = stage[k];
         }
         wave_lds_sync();  // the stage is rewritten by the next chunk
       }
