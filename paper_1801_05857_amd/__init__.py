@@ -300,6 +300,7 @@ class Table:
         h = ctypes.c_void_p()
         _check(lib().gx_table_create(words_per_state, bucket_words, capacity,
                                      ctypes.byref(opts), ctypes.byref(h)), "gx_table_create")
+        self._destroy = lib().gx_table_destroy
         self._h = h
         self.info = self._info()
 
@@ -311,7 +312,9 @@ class Table:
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
-            lib().gx_table_destroy(self._h)
+            # the destroy function is held by the object: at interpreter exit
+            # the module's globals may already be gone when __del__ runs
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -604,11 +607,14 @@ class Batch:
         h = ctypes.c_void_p()
         _check(lib().gx_batch_create(arr, self.n, ctypes.byref(opts), ctypes.byref(h)),
                "gx_batch_create")
+        self._destroy = lib().gx_batch_destroy
         self._h = h
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
-            lib().gx_batch_destroy(self._h)
+            # the destroy function is held by the object: at interpreter exit
+            # the module's globals may already be gone when __del__ runs
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -656,11 +662,14 @@ class Server:
                            bucket_words, subgroup, keys_per_subgroup, int(keep_states))
         h = ctypes.c_void_p()
         _check(lib().gx_server_create(ctypes.byref(opts), ctypes.byref(h)), "gx_server_create")
+        self._destroy = lib().gx_server_destroy
         self._h = h
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
-            lib().gx_server_destroy(self._h)
+            # the destroy function is held by the object: at interpreter exit
+            # the module's globals may already be gone when __del__ runs
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
