@@ -236,6 +236,27 @@ def cpu_baseline(target_s: float = 15.0):
                       f"(2^{k} distinct, each twice, shuffled), one thread, {dt:.1f} s"}
 
 
+def claim_ceiling(gx, torch, mode: int, gib: int = 2, n_ops: int = 1 << 28):
+    """Operations per second of gx_claim_probe over a `gib` GiB buffer: mode 1
+    device-scope compare-and-swaps at random 64-byte granules, mode 2 an
+    8-byte read each with a compare-and-swap in the same granule for every
+    other one (find-or-put of keys half of which are new)."""
+    buf = torch.full((gib << 27,), -1, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gx.claim_probe(buf, mode, n_ops, 7, sink)
+    torch.cuda.synchronize()
+    buf.fill_(-1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    gx.claim_probe(buf, mode, n_ops, 11, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = n_ops / (e0.elapsed_time(e1) * 1e-3)
+    del buf
+    torch.cuda.empty_cache()
+    return rate
+
+
 def random_read_ceiling(gx, torch, granule: int, gib: int = 2):
     """Random reads of `granule` bytes per second over a `gib` GiB buffer
     (gx_gather_probe): the achievable ceiling of one bucket probe."""
@@ -793,6 +814,12 @@ def main():
                                   "GB_per_s_useful": n_reads * g / ms / 1e6}), flush=True)
             del buf
             torch.cuda.empty_cache()
+            for mode, what in ((1, "compare-and-swap at a random 64-byte granule"),
+                               (2, "8-byte read, compare-and-swap in that granule for every "
+                                   "other operation")):
+                rate = claim_ceiling(gx, torch, mode, gib)
+                print(json.dumps({"footprint_GiB": gib, "claim_probe": what,
+                                  "Gops_per_s": round(rate / 1e9, 3)}), flush=True)
         return
 
     if args.dup_sweep:
@@ -938,6 +965,16 @@ def main():
     out["roofline"]["random_read_ceiling"] = {
         "granule_bytes": max(4 * args.bucket, GRANULE), "G_reads_per_s": round(ceil / 1e9, 2),
         "probes_per_s_frac": round(n * r["probes_per_op"] / (r["fop_ms"] * 1e-3) / ceil, 4)}
+    # what the claims cost: device-scope compare-and-swaps alone, and the
+    # read-then-claim mix of a stream whose keys are half new, on a buffer
+    # of the table's size
+    gib = max(1, int(round(r["table_bytes"] / (1 << 30))))
+    cas = claim_ceiling(gx, torch, 1, gib)
+    mix = claim_ceiling(gx, torch, 2, gib)
+    out["roofline"]["claim_ceiling"] = {
+        "footprint_GiB": gib, "G_cas_per_s": round(cas / 1e9, 2),
+        "G_read_then_half_claim_ops_per_s": round(mix / 1e9, 2),
+        "ops_per_s_frac_of_mix": round(n / (r["fop_ms"] * 1e-3) / mix, 4)}
     # the same keys as 2^20-key launches back to back (one batch vs sub-batches)
     sub_ms, sub_new, sub_full = run_fop_sub_batches(gx, torch, keys, n_distinct, args.bucket,
                                                     args.subgroup, args.kps, args.alpha, H,

@@ -607,6 +607,20 @@ gx_status gx_server_destroy(gx_server* server);
 gx_status gx_gather_probe(const uint32_t* buf, uint64_t buf_bytes, uint32_t granule,
                           uint64_t n_reads, uint64_t seed, uint64_t* sink, void* hip_stream);
 
+/*
+ * Claim probe: n_ops operations at pseudo-random 64-byte-aligned offsets of
+ * a device buffer of buf_bytes bytes (>= 64, 64-byte aligned).  mode 1: one
+ * device-scope 64-bit compare-and-swap each (the claim of a find-or-put,
+ * Sec. 4.1); mode 2: an 8-byte read each and, for every other operation, a
+ * compare-and-swap in the granule just read (a find-or-put of keys half of
+ * which are new).  The buffer's contents are changed; a value derived from
+ * them is added to *sink (device, 8 bytes).  Stream-ordered.  Gives the
+ * ceiling that claims put on find-or-put.  Errors: GX_EINVAL (null, too
+ * small or misaligned buffer, other modes), GX_EDEVICE (launch).
+ */
+gx_status gx_claim_probe(uint64_t* buf, uint64_t buf_bytes, uint32_t mode, uint64_t n_ops,
+                         uint64_t seed, uint64_t* sink, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

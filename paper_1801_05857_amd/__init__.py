@@ -35,7 +35,7 @@ EXPORTED = [
     "gx_batch_destroy", "gx_explore_batch", "gx_autotune", "gx_autotune_capacity",
     "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_get_stats",
     "gx_server_destroy", "gx_network_add_monitor", "gx_monitored_network_free",
-    "gx_explore_noalloc",
+    "gx_explore_noalloc", "gx_claim_probe",
 ]
 
 
@@ -203,6 +203,8 @@ def lib() -> ctypes.CDLL:
         L.gx_explore_result_free.argtypes = [ctypes.POINTER(_ExploreResult)]
         L.gx_status_str.restype = ctypes.c_char_p
         L.gx_status_str.argtypes = [st]
+        L.gx_claim_probe.restype = st
+        L.gx_claim_probe.argtypes = [vp, u64, u32, u64, u64, vp, vp]
         L.gx_gather_probe.restype = st
         L.gx_gather_probe.argtypes = [vp, u64, u32, u64, u64, vp, vp]
         L.gx_batch_create.restype = st
@@ -566,6 +568,13 @@ def gather_probe(buf, granule: int, n_reads: int, seed: int, sink, stream=None) 
     _check(lib().gx_gather_probe(_dev_ptr(buf, "buf"), buf.numel() * buf.element_size(),
                                  granule, n_reads, seed, _dev_ptr(sink, "sink"),
                                  _stream_handle(stream)), "gx_gather_probe")
+
+
+def claim_probe(buf, mode: int, n_ops: int, seed: int, sink, stream=None) -> None:
+    """gx_claim_probe on a device tensor `buf` (1: compare-and-swaps, 2: reads
+    with a compare-and-swap for every other one); sink: a device int64 tensor."""
+    _check(lib().gx_claim_probe(buf.data_ptr(), buf.numel() * buf.element_size(), mode, n_ops,
+                                seed, sink.data_ptr(), _stream_handle(stream)), "gx_claim_probe")
 
 
 # ------------------------------------------------------------------ batches

@@ -65,6 +65,45 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(const uint32_t* buf, 
   if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(sink), acc);
 }
 
+// Device-scope claim probe: n_ops operations at pseudo-random 64-byte
+// granules, four in flight per lane.  Mode 1: one 64-bit compare-and-swap
+// each.  Mode 2: an 8-byte read each and, for every other operation, a
+// 64-bit compare-and-swap in the granule just read: the read-then-claim
+// pattern of a find-or-put whose keys are half new.
+__global__ __launch_bounds__(256) void claim_probe_kernel(uint64_t* buf, uint64_t n_gran,
+                                                          uint64_t n_ops, uint32_t mode,
+                                                          uint64_t seed, uint64_t* sink) {
+  constexpr int R = 4;
+  const uint64_t tid = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t n_threads = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t acc = 0;
+  for (uint64_t base = tid * R; base < n_ops; base += n_threads * R) {
+    uint64_t g[R], v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t idx = base + r;
+      g[r] = idx < n_ops ? mulhi64(fmix64(seed ^ (idx * kGolden)), n_gran) : 0;
+      v[r] = 0;
+    }
+    if (mode == 2) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (base + r < n_ops) v[r] = buf[g[r] * 8];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t idx = base + r;
+      if (idx < n_ops && (mode == 1 || (idx & 1)))
+        v[r] += atomicCAS(reinterpret_cast<unsigned long long*>(buf + g[r] * 8 + 1 + (v[r] & 1)),
+                          ~0ull, static_cast<unsigned long long>(idx | 1));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc += v[r];
+  }
+  const uint32_t lo = wave_sum(static_cast<uint32_t>(acc));
+  if (__lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(sink), lo);
+}
+
 // ------------------------------------------------------------------ dispatch
 uint32_t resident_grid(int device, uint32_t per_cu) {
   int cus = 0;
@@ -410,6 +449,20 @@ gx_status gx_hash_bucket(const uint32_t* key, uint32_t w, uint64_t seed, uint32_
   }
   *bucket = gx::bucket_of(mix, a, c, n_buckets);
   return GX_OK;
+}
+
+gx_status gx_claim_probe(uint64_t* buf, uint64_t buf_bytes, uint32_t mode, uint64_t n_ops,
+                         uint64_t seed, uint64_t* sink, void* stream) {
+  if (!buf || !sink || buf_bytes < 64 || (mode != 1 && mode != 2)) return GX_EINVAL;
+  if (reinterpret_cast<uintptr_t>(buf) % 64 != 0) return GX_EINVAL;
+  if (n_ops == 0) return GX_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GX_EDEVICE;
+  const uint32_t grid = static_cast<uint32_t>(std::max<uint64_t>(
+      1, std::min<uint64_t>((n_ops + 1023) / 1024, gx::resident_grid(dev, 8))));
+  hipLaunchKernelGGL(gx::claim_probe_kernel, dim3(grid), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), buf, buf_bytes / 64, n_ops, mode, seed, sink);
+  return hipGetLastError() == hipSuccess ? GX_OK : GX_EDEVICE;
 }
 
 gx_status gx_gather_probe(const uint32_t* buf, uint64_t buf_bytes, uint32_t granule,

@@ -66,6 +66,11 @@ def test_null_handles_rejected(lib):
     assert lib.gx_explore(None, None, None, None) == gx.GX_EINVAL
     assert lib.gx_table_destroy(None) == gx.GX_OK
     assert lib.gx_gather_probe(None, 0, 64, 1, 0, None, None) == gx.GX_EINVAL
+    assert lib.gx_claim_probe(None, 64, 1, 1, 0, None, None) == gx.GX_EINVAL
+    buf = ctypes.c_void_p(64)
+    assert lib.gx_claim_probe(buf, 32, 1, 1, 0, buf, None) == gx.GX_EINVAL   # too small
+    assert lib.gx_claim_probe(buf, 4096, 3, 1, 0, buf, None) == gx.GX_EINVAL  # no mode 3
+    assert lib.gx_claim_probe(ctypes.c_void_p(72), 4096, 1, 1, 0, buf, None) == gx.GX_EINVAL
 
 
 def _bad_nets():
