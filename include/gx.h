@@ -313,8 +313,10 @@ typedef struct {
  * the table's find-or-put; states it reports NEW form the next level.
  *
  *   net    host description; compiled to a device image for the call.
- *   table  caller-created, empty, with words_per_state equal to
- *          gx_network_words(net); it holds the reachable set afterwards.
+ *   table  caller-created, empty (nothing inserted since its creation or
+ *          its last gx_table_clear; else GX_EINVAL before any device work),
+ *          with words_per_state equal to gx_network_words(net); it holds the
+ *          reachable set afterwards.
  *   opts   nullable.
  *   out    filled on success; free with gx_explore_result_free.
  *

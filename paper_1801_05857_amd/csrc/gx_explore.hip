@@ -475,6 +475,8 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
   if (ni.words != t->w) return GX_EINVAL;
   const bool monitor = opts && opts->monitor_bad;
   if (monitor && (fixed || opts->monitor_proc >= ni.field.size())) return GX_EINVAL;
+  // the table must be empty: its first levels are placed assuming so
+  if (t->holds_states) return GX_EINVAL;
   const uint32_t S = t->S;
   const size_t state_bytes = S * sizeof(uint32_t);
   // 0: limited only by device memory
@@ -556,6 +558,7 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
   uint64_t* ctr_raw = eb.ctr_host;
   const gx::SmallOut* small_out = reinterpret_cast<const gx::SmallOut*>(ctr_raw + kCtrWords);
   auto ctr = [&](uint32_t k) { return ctr_raw[k * gx::kCtrSpread]; };
+  t->holds_states = true;  // from here on the exploration writes the table
   {
     // zeroed counters, the initial state's whole slot (a 3-word state's
     // fourth word is 0) and the image, up in one copy from pinned memory

@@ -53,6 +53,9 @@ struct gx_table {
   uint64_t* counters = nullptr;  // ctr_slots sets of gx::kNumCounters
   uint32_t ctr_slots = 1;
   uint64_t a0 = 0, c0 = 0;
+  // something was inserted since creation or the last clear: gx_explore, whose
+  // first levels place states assuming an empty table, refuses the table
+  bool holds_states = false;
   gx_explore_buffers eb;
 
   gx::TableDev dev() const {

@@ -260,6 +260,58 @@ __device__ inline bool lds_set_insert(uint32_t* set, uint32_t mask, const uint32
   return fresh;
 }
 
+// The logged states into the table, by the workgroup that logged them, with
+// no device-scope claim: the table held none of them and nothing else (the
+// premise of an LDS-resident launch) and they are distinct (the visited set
+// decided that), so each takes the next slot of the first bucket of its hash
+// sequence that still has one, counted in LDS (fill, one word per bucket),
+// and is written with a plain store.  That is the layout find-or-put builds:
+// a bucket fills from its lowest slot, and a state lies in its j-th bucket
+// only when buckets 1..j-1 of its sequence are full.  (Claimed one by one,
+// the states of a small fresh table queue at a few memory channels: 29 us
+// for 4096 of them.)  No slot left in any of the H buckets: FULL.  Log entry
+// 0 is the initial state; its outcome goes to out->init_status.  Must be
+// reached by the whole workgroup.
+template <int S, int B>
+__device__ inline void place_log(const SmallArgs& a, uint32_t* fill, const uint32_t* log,
+                                 uint32_t log_n) {
+  constexpr uint32_t kSlots = B / S;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nb = static_cast<uint32_t>(a.t.n_buckets);
+  for (uint32_t k = tid; k < nb; k += kSmallThreads) fill[k] = 0;
+  __syncthreads();
+  LaneStats st;
+  uint32_t stored = 0, lookups = 0, full = 0;
+  for (uint32_t i = tid; i < log_n; i += kSmallThreads) {
+    uint32_t key[S];
+    load_slot<S>(log + static_cast<uint64_t>(i) * S, key);
+    const uint64_t mix = key_mix<S>(key, a.t.seed);
+    bool done = false;
+    uint32_t j = 0;
+    for (; j < a.t.H && !done; ++j) {
+      const uint64_t ca = j == 0 ? a.t.a0 : a.t.hc[2 * j];
+      const uint64_t cc = j == 0 ? a.t.c0 : a.t.hc[2 * j + 1];
+      const uint64_t b = bucket_of(mix, ca, cc, a.t.n_buckets);
+      const uint32_t slot = atomicAdd(&fill[b], 1u);
+      ++st.probes;
+      if (slot < kSlots) {
+        store_slot<S>(a.t.words + b * B + slot * S, key);
+        done = true;
+        if (j > st.max_j) st.max_j = j;
+      }
+    }
+    ++lookups;
+    if (done) ++stored;
+    else ++full;
+    if (i == 0) a.out->init_status = done ? kNew : kFull;
+  }
+  st.stored = wave_sum(stored);
+  st.lookups = wave_sum(lookups);
+  st.full = wave_sum(full);
+  if (st.full && __lane_id() == 0) atomicOr(ctr_at(a.ctr, kCtrFlags), kFlagTableFull);
+  flush_stats(a.t, st, nullptr);
+}
+
 // The first levels of an exploration, while the table holds nothing but what
 // this launch puts there: an LDS set of every state reached so far decides
 // NEW or SEEN exactly, with no table probe.  New states are appended to a log
@@ -268,8 +320,10 @@ __device__ inline bool lds_set_insert(uint32_t* set, uint32_t mask, const uint32
 // stays at most three quarters full even if every successor were new.  When
 // the levels end (the exploration is complete, a level would not fit, or
 // kSmallLevels levels are done) the current level is copied to frontier
-// buffer 0 for the host, and log_insert_kernel puts every logged state into
-// the table.
+// buffer 0 for the host, and every logged state goes into the table: placed
+// by this workgroup when the table's per-bucket fill counts fit in the LDS
+// the visited set used (see place_log), else by log_insert_kernel, launched
+// after it.
 template <int S, int B, int G, int U>
 __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) {
   extern __shared__ uint32_t smem[];
@@ -405,14 +459,17 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
   }
   __syncthreads();
   // the current level becomes frontier buffer 0 (when the levels go on)
-  const uint32_t ls = sh_ls, n_cur = sh_le - sh_ls;
+  const uint32_t ls = sh_ls, n_cur = sh_le - sh_ls, log_n = sh_log_n;
   for (uint32_t k = tid; k < n_cur * S; k += kSmallThreads)
     a.f[0][k] = log[static_cast<uint64_t>(ls) * S + k];
+  // the visited set is done with: its LDS holds the bucket fill counts
+  const bool placed = a.t.n_buckets <= static_cast<uint64_t>(n_set) * S;
+  if (placed) place_log<S, B>(a, set, log, log_n);
   if (tid == 0) {
     a.out->n_levels = sh_levels;
     a.out->n_in = n_cur;  // 0: the last level expanded found nothing new
     a.out->cur = 0;
-    a.out->log_n = sh_log_n;
+    a.out->log_n = placed ? 0 : log_n;  // states left for log_insert_kernel
     if (sh_trans) atomicAdd(ctr_at(a.ctr, kCtrTrans), sh_trans);
   }
 }

@@ -339,8 +339,9 @@ gx_status gx_table_destroy(gx_table* t) {
 
 gx_status gx_table_clear(gx_table* t, void* stream) {
   if (!t) return GX_EINVAL;
-  return gx::clear_storage(t, static_cast<hipStream_t>(stream)) == hipSuccess ? GX_OK
-                                                                              : GX_EDEVICE;
+  if (gx::clear_storage(t, static_cast<hipStream_t>(stream)) != hipSuccess) return GX_EDEVICE;
+  t->holds_states = false;
+  return GX_OK;
 }
 
 gx_status gx_find_or_put(gx_table* t, const uint32_t* keys, uint64_t n, uint8_t* status,
@@ -351,6 +352,7 @@ gx_status gx_find_or_put(gx_table* t, const uint32_t* keys, uint64_t n, uint8_t*
   const uintptr_t align = t->S == 1 ? 4 : (t->S == 2 ? 8 : (t->w == 4 ? 16 : 4));
   if (reinterpret_cast<uintptr_t>(keys) % align != 0) return GX_EINVAL;
   if (n_new && reinterpret_cast<uintptr_t>(n_new) % 8 != 0) return GX_EINVAL;
+  t->holds_states = true;
   return gx::launch_find_or_put(t, keys, n, status, n_new, static_cast<hipStream_t>(stream)) ==
                  hipSuccess
              ? GX_OK

@@ -185,6 +185,22 @@ def test_non_empty_table_rejected(dev):
         assert got.n_states == 216
 
 
+def test_table_with_inserted_keys_rejected(dev):
+    """A table that received keys through find-or-put is not empty: refused
+    before any device work, accepted again once cleared."""
+    net = W.token_ring(4)
+    with gx.Table(1, 32, 1024) as t:
+        keys = torch.tensor([[5]], dtype=torch.int32, device=dev)
+        status = torch.empty(1, dtype=torch.uint8, device=dev)
+        t.find_or_put(keys, status)
+        with pytest.raises(gx.GxError) as e:
+            gx.explore(net, t)
+        assert e.value.code == gx.GX_EINVAL
+        assert t.dump().shape[0] == 1  # untouched
+        t.clear()
+        assert gx.explore(net, t).n_states == 216
+
+
 def test_word_count_mismatch_rejected(dev):
     with gx.Table(2, 32, 1024) as t:
         with pytest.raises(gx.GxError) as e:
