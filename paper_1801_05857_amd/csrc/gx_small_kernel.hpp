@@ -540,7 +540,10 @@ hipError_t launch_lds_b(const SmallArgs& a, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((lds_levels_kernel<S, B, G, U>), dim3(1), dim3(kSmallThreads), lds, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // the logged states (at most three quarters of the set) into the table
+  // the launch places its log itself when the table's fill counts fit the
+  // set's LDS (the test place_log's caller makes)
+  if (a.t.n_buckets <= (static_cast<uint64_t>(a.set_mask) + 1) * S) return hipSuccess;
+  // else the logged states (at most three quarters of the set) into the table
   const uint32_t grid = static_cast<uint32_t>(
       std::min<uint64_t>(256, (static_cast<uint64_t>(a.set_mask) + 1) / 256 + 1));
   hipLaunchKernelGGL((log_insert_kernel<S, B, G, U>), dim3(grid), dim3(256), 0, s, a.t, a.succ,
