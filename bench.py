@@ -281,7 +281,9 @@ def run_tiny(gx, torch, W, reps=10):
     """The tiny configuration (four 8-state cycles with two rendezvous, one
     word, table of 2^16 words, buckets of 32): microseconds per exploration,
     median of `reps` after warm-up."""
-    net = W.tiny_cycles()
+    # the network's ctypes view is built once, as a C caller builds its
+    # gx_network once for repeated calls
+    net = gx.network_view(W.tiny_cycles())
     t = gx.Table(1, 32, 1 << 16, subgroup=8, max_hashes=16)
     times = []
     for k in range(reps + 3):

@@ -391,12 +391,17 @@ def hash_bucket(key, words_per_state: int, hash_seed: int, j: int, n_buckets: in
 
 
 # ------------------------------------------------------------------ networks
-class _NetHolder:
+class NetworkView:
     """ctypes view of a network object (n_states, initial, trans, n_labels,
-    rules); keeps the arrays alive while the library reads them."""
+    rules) as the library reads it; keeps its arrays alive.  Every call that
+    takes a network also takes a view (network_view), so a caller that
+    explores one network again and again marshals it once.  The view holds
+    copies of the network's arrays: later changes to the network are not
+    seen through it."""
 
     def __init__(self, net):
         P = len(net.n_states)
+        self.n_procs = P
         self.arrays = []
         procs = (_Lts * P)()
         for p in range(P):
@@ -409,6 +414,14 @@ class _NetHolder:
         self.arrays += [rules, procs]
         self.c = _Network(P, procs, int(net.n_labels), rules.shape[0],
                           rules.ctypes.data if rules.size else None)
+
+
+_NetHolder = NetworkView
+
+
+def network_view(net) -> NetworkView:
+    """The network's ctypes view, built once for repeated calls."""
+    return net if isinstance(net, NetworkView) else NetworkView(net)
 
 
 @dataclass
@@ -435,7 +448,7 @@ def add_monitor(net, automaton, bad) -> tuple:
     src, act, dst = (np.ascontiguousarray(t[:, i]) for i in range(3))
     flags = np.zeros(max(1, int(n)), dtype=np.uint8)
     flags[list(bad)] = 1
-    h = _NetHolder(net)
+    h = network_view(net)
     mon = _Monitor(int(n), int(init), t.shape[0], src.ctypes.data, act.ctypes.data,
                    dst.ctypes.data, flags.ctypes.data)
     out = _MonitoredNetwork()
@@ -469,17 +482,17 @@ def add_monitor(net, automaton, bad) -> tuple:
 
 
 def network_words(net) -> int:
-    h = _NetHolder(net)
+    h = network_view(net)
     w = ctypes.c_uint32()
     _check(lib().gx_network_words(ctypes.byref(h.c), ctypes.byref(w)), "gx_network_words")
     return int(w.value)
 
 
 def network_pack(net, local) -> np.ndarray:
-    h = _NetHolder(net)
-    P = len(net.n_states)
+    h = network_view(net)
+    P = h.n_procs
     loc = np.ascontiguousarray(local, dtype=np.uint32).reshape(-1, P)
-    w = network_words(net)
+    w = network_words(h)
     out = np.empty((loc.shape[0], w), dtype=np.uint32)
     _check(lib().gx_network_pack(ctypes.byref(h.c), loc.ctypes.data, loc.shape[0],
                                  out.ctypes.data), "gx_network_pack")
@@ -527,12 +540,12 @@ def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity:
             stop_on_violation: bool = False) -> ExploreResult:
     """gx_explore: BFS of the synchronous product into ``table``.  monitor =
     (process, bad flags per local state of it) checks a safety property."""
-    h = _NetHolder(net)
+    h = network_view(net)
     proc, bad = 0, None
     if monitor is not None:
         proc = int(monitor[0])
         bad = np.ascontiguousarray(np.asarray(monitor[1]).astype(np.uint8))
-        if not 0 <= proc < len(net.n_states) or bad.shape != (int(net.n_states[proc]),):
+        if not 0 <= proc < h.n_procs or bad.shape != (int(h.c.procs[proc].n_states),):
             raise ValueError("monitor: a process index and one flag per local state of it")
     opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream),
                         int(local_dedup), proc, int(stop_on_violation), 0,
@@ -549,7 +562,7 @@ def explore_noalloc(net, table: Table, *, max_levels: int = 4096, max_deadlocks:
     """gx_explore_noalloc: gx_explore with the library's static scratch array
     for its device buffers and results in host arrays passed in (here numpy
     arrays of max_levels and max_deadlocks entries)."""
-    h = _NetHolder(net)
+    h = network_view(net)
     w = table.info.words_per_state
     levels = np.zeros(max(1, max_levels), dtype=np.uint64)
     dead = np.zeros((max(1, max_deadlocks), w), dtype=np.uint32)
@@ -605,7 +618,7 @@ class Batch:
                  use_graph: bool = False, max_levels: int = 0, deadlock_capacity: int = 0,
                  keep_states: bool = False, persistent: bool = False):
         self.n = len(nets)
-        holders = [_NetHolder(net) for net in nets]
+        holders = [network_view(net) for net in nets]
         arr = (_Network * self.n)(*[h.c for h in holders])
         cap = np.ascontiguousarray(capacity, dtype=np.uint64).reshape(-1)
         if cap.shape[0] != self.n:
@@ -690,7 +703,7 @@ class Server:
         self.close()
 
     def submit(self, net, declared_states: int) -> int:
-        h = _NetHolder(net)
+        h = network_view(net)
         rid = ctypes.c_uint64()
         _check(lib().gx_server_submit(self._h, ctypes.byref(h.c), declared_states,
                                       ctypes.byref(rid)), "gx_server_submit")

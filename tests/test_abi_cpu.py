@@ -234,3 +234,14 @@ def test_networks_with_images_beyond_lds_compile(lib):
     assert gx.network_words(net) == 2
     packed = gx.network_pack(net, np.zeros((1, 4), dtype=np.uint32))
     assert packed.shape == (1, 2) and not packed.any()
+
+
+def test_network_view_is_accepted_wherever_a_network_is(lib):
+    """network_view builds the ctypes view once; the host-side calls take it
+    in place of the network."""
+    net = W.random_lts(21, 4, 4096, 12, 3, 32, 0.25, 0.1)
+    v = gx.network_view(net)
+    assert gx.network_view(v) is v
+    assert gx.network_words(v) == gx.network_words(net) == 2
+    loc = np.array([[1, 2, 3, 4]], dtype=np.uint32)
+    assert np.array_equal(gx.network_pack(v, loc), gx.network_pack(net, loc))

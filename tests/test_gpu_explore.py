@@ -287,3 +287,17 @@ def test_deadlock_capacity(dev, cap, ok):
             with pytest.raises(gx.GxError) as e:
                 gx.explore(net, t, deadlock_capacity=cap)
             assert e.value.code == gx.GX_ENOMEM
+
+
+def test_explore_through_a_network_view(dev):
+    """A network view built once serves repeated explorations."""
+    net = W.token_ring(7)
+    want = oracle.explore(net, want_visited=True)
+    view = gx.network_view(net)
+    with gx.Table(1, 32, 4 * want.n_states) as t:
+        for _ in range(3):
+            t.clear()
+            got = gx.explore(view, t)
+            assert got.levels.tolist() == want.levels.tolist()
+            assert got.n_transitions == want.n_transitions
+        assert np.array_equal(t.dump(), want.visited)
