@@ -597,10 +597,12 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
                                                           cfg[0], 4 if r.words_per_state == 3
                                                           else r.words_per_state)
                      for (st, r), cfg in zip(res, cfgs) if st == gx.GX_OK)
-    # one exploration per instance, tables and buffers resident
+    # one exploration per instance, tables, buffers and the networks' ctypes
+    # views resident (the batch marshals its networks once, at creation)
+    views = [gx.network_view(nt) for nt in nets]
     tables = [gx.Table(gx.network_words(nt), B, c, subgroup=G, keys_per_subgroup=U,
-                       max_hashes=hashes) for nt, c, (B, G, U) in zip(nets, caps, cfgs)]
-    for nt, t in zip(nets, tables):
+                       max_hashes=hashes) for nt, c, (B, G, U) in zip(views, caps, cfgs)]
+    for nt, t in zip(views, tables):
         try:
             gx.explore(nt, t)  # sizes each table's resident buffers
         except gx.GxError:
@@ -610,7 +612,7 @@ def run_batch(gx, torch, W, n, seed=11, hashes=16, B=0, G=0, U=0):
     single_states = 0
     mismatch = 0
     single_failed = 0
-    for k, (nt, t) in enumerate(zip(nets, tables)):
+    for k, (nt, t) in enumerate(zip(views, tables)):
         t.clear()
         try:
             r = gx.explore(nt, t)
@@ -696,7 +698,7 @@ def run_serve(gx, torch, W, n_req=1000, seed=5, rates=(0.1, 0.25, 0.5, 0.75, 1.0
     t_net = {}
     cfg_of = {}
     for i in sorted(set(reqs)):
-        nt = nets[i]
+        nt = gx.network_view(nets[i])
         w = gx.network_words(nt)
         tb, tg, _ = gx.autotune(w, 0.5)  # the server's kernel configuration
         cfg_of[i] = (tb, 4 if w == 3 else w)
