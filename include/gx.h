@@ -279,7 +279,10 @@ typedef struct {
   uint32_t stop_on_violation; /* nonzero: end the exploration after the first
                                  level that holds a violation (that level is
                                  counted, not expanded)                        */
-  uint32_t reserved;
+  uint32_t slice_states;      /* most frontier states one slice of a level
+                                 takes (one generation launch, then one probe
+                                 launch, whose successor buffer holds the
+                                 slice's successors); 0 -> 2^22               */
   const uint8_t* monitor_bad; /* host, n_states of monitor_proc bytes, nonzero
                                  = bad local state; NULL: no safety check      */
 } gx_explore_opts;

@@ -82,7 +82,7 @@ class _ExploreOpts(ctypes.Structure):
     _fields_ = [("frontier_capacity", ctypes.c_uint64), ("deadlock_capacity", ctypes.c_uint64),
                 ("hip_stream", ctypes.c_void_p), ("local_dedup", ctypes.c_uint32),
                 ("monitor_proc", ctypes.c_uint32), ("stop_on_violation", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("monitor_bad", ctypes.c_void_p)]
+                ("slice_states", ctypes.c_uint32), ("monitor_bad", ctypes.c_void_p)]
 
 
 class _ExploreResult(ctypes.Structure):
@@ -537,9 +537,10 @@ def _take_result(res: _ExploreResult) -> ExploreResult:
 
 def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity: int = 0,
             stream=None, local_dedup: bool = False, monitor=None,
-            stop_on_violation: bool = False) -> ExploreResult:
+            stop_on_violation: bool = False, slice_states: int = 0) -> ExploreResult:
     """gx_explore: BFS of the synchronous product into ``table``.  monitor =
-    (process, bad flags per local state of it) checks a safety property."""
+    (process, bad flags per local state of it) checks a safety property;
+    slice_states: most frontier states per slice of a level (0: 2^22)."""
     h = network_view(net)
     proc, bad = 0, None
     if monitor is not None:
@@ -548,7 +549,7 @@ def explore(net, table: Table, *, frontier_capacity: int = 0, deadlock_capacity:
         if not 0 <= proc < h.n_procs or bad.shape != (int(h.c.procs[proc].n_states),):
             raise ValueError("monitor: a process index and one flag per local state of it")
     opts = _ExploreOpts(frontier_capacity, deadlock_capacity, _stream_handle(stream),
-                        int(local_dedup), proc, int(stop_on_violation), 0,
+                        int(local_dedup), proc, int(stop_on_violation), int(slice_states),
                         bad.ctypes.data if bad is not None else None)
     res = _ExploreResult()
     _check(lib().gx_explore(ctypes.byref(h.c), table.handle, ctypes.byref(opts),

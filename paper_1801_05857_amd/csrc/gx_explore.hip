@@ -674,7 +674,8 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
   uint64_t n_in = 1;
   int cur = 0;
   uint64_t dead_known = 0;
-  constexpr uint64_t kTargetSlice = 1u << 22;  // 16384 workgroups per launch
+  // 16384 workgroups per launch unless the caller asks for less
+  const uint64_t kTargetSlice = opts && opts->slice_states ? opts->slice_states : 1u << 22;
   constexpr uint64_t kMaxRoom = 1ull << 28;    // states of frontier room one slice may claim
   uint64_t slice_no = 0;  // successor counters alternate from slice to slice
   bool init_inserted = small_limit == 0;

@@ -275,6 +275,28 @@ def test_small_and_large_levels_alternate(dev):
         _explore_and_compare(net, B=B, check_dump=(B == 16))
 
 
+@pytest.mark.parametrize("dedup", [False, True])
+@pytest.mark.parametrize("slice_states,frontier", [(256, 0), (1000, 0), (700, 1 << 16)])
+def test_many_slices_per_level(dev, dedup, slice_states, frontier):
+    """Slices of a few hundred states cut the levels of the 248,832-state
+    network (up to about 30,000 states) into many, their successor counters
+    alternating; with a frontier capacity of 2^16 the room also runs out
+    within levels and read-backs come between slices.  Three explorations in
+    a row into one table."""
+    net = W.large_random_network(live=4)
+    want = oracle.explore(net, want_visited=True)
+    with gx.Table(want.words, 16, 2 * want.n_states, max_hashes=64) as t:
+        for _ in range(3):
+            t.clear()
+            got = gx.explore(net, t, frontier_capacity=frontier, local_dedup=dedup,
+                             slice_states=slice_states)
+            assert got.n_states == want.n_states
+            assert got.levels.tolist() == want.levels.tolist()
+            assert got.n_transitions == want.n_transitions
+            assert np.array_equal(got.deadlocks, want.deadlocks)
+            assert np.array_equal(t.dump(), want.visited)
+
+
 @pytest.mark.parametrize("cap,ok", [(1, False), (255, False), (256, True)])
 def test_deadlock_capacity(dev, cap, ok):
     """wide_rule(4, 4): 256 deadlocks, all in level 1."""
