@@ -88,12 +88,13 @@ class _ExploreOpts(ctypes.Structure):
 class _ExploreResult(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_uint64), ("n_transitions", ctypes.c_uint64),
                 ("words_per_state", ctypes.c_uint32), ("n_levels", ctypes.c_uint32),
-                ("level_counts", ctypes.POINTER(ctypes.c_uint64)),
-                ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.POINTER(ctypes.c_uint32)),
+                # (library-owned arrays as plain addresses: copied out by _take_result)
+                ("level_counts", ctypes.c_void_p),
+                ("n_deadlocks", ctypes.c_uint64), ("deadlocks", ctypes.c_void_p),
                 ("local_duplicates", ctypes.c_uint64),
-                ("n_violations", ctypes.c_uint64), ("violations", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_violations", ctypes.c_uint64), ("violations", ctypes.c_void_p),
                 ("violation_level", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("states", ctypes.POINTER(ctypes.c_uint32))]
+                ("states", ctypes.c_void_p)]
 
 
 class _Monitor(ctypes.Structure):
@@ -253,6 +254,11 @@ def _stream_handle(stream) -> int:
     import torch
 
     if stream is None:
+        # torch's current stream, as a raw handle (without building a Stream
+        # object where torch offers that)
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return int(raw(torch.cuda.current_device()) or 0)
         stream = torch.cuda.current_stream()
     return int(getattr(stream, "cuda_stream", stream) or 0)
 
@@ -512,22 +518,22 @@ class ExploreResult:
     states: np.ndarray = None  # (n_states, w) uint32, sorted (keep_states of batches, servers)
 
 
+def _copy_out(addr, n: int, dtype) -> np.ndarray:
+    """A numpy copy of n elements at a library-owned host address."""
+    if not n or not addr:
+        return np.zeros(0, dtype)
+    return np.frombuffer(ctypes.string_at(addr, n * np.dtype(dtype).itemsize), dtype=dtype).copy()
+
+
 def _take_result(res: _ExploreResult) -> ExploreResult:
     w = res.words_per_state
-    levels = np.ctypeslib.as_array(res.level_counts, shape=(res.n_levels,)).copy()
-    if res.n_deadlocks:
-        dead = np.ctypeslib.as_array(res.deadlocks, shape=(res.n_deadlocks * w,)).copy()
-    else:
-        dead = np.zeros(0, np.uint32)
-    if res.n_violations:
-        viol = np.ctypeslib.as_array(res.violations, shape=(res.n_violations * w,)).copy()
-    else:
-        viol = np.zeros(0, np.uint32)
+    levels = _copy_out(res.level_counts, res.n_levels, np.uint64)
+    dead = _copy_out(res.deadlocks, res.n_deadlocks * w, np.uint32)
+    viol = _copy_out(res.violations, res.n_violations * w, np.uint32)
     vl = None if res.violation_level == 0xFFFFFFFF else int(res.violation_level)
     states = None
     if res.states:
-        states = np.ctypeslib.as_array(res.states, shape=(max(1, res.n_states * w),))
-        states = states[: res.n_states * w].copy().reshape(-1, w)
+        states = _copy_out(res.states, res.n_states * w, np.uint32).reshape(-1, w)
     out = ExploreResult(int(res.n_states), int(res.n_transitions), w, levels,
                         dead.reshape(-1, w), int(res.local_duplicates), viol.reshape(-1, w), vl,
                         states)
