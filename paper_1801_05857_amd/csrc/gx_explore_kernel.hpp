@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <type_traits>
 
 #include "gx_internal.hpp"
 
@@ -139,16 +140,16 @@ __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t 
     return false;
   };
   // successors: `from` with field f set to each of img[s0 .. s0 + n); targets
-  // are read from LDS four at a time before any successor of the group is
-  // formed, so one LDS round trip serves up to four successors
-  auto run = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t n) {
-    if (below(n)) return;
-    for (uint32_t t = 0; cur < hi && __ballot(t < n); t += 4) {
-      uint32_t d[4];
+  // are read from LDS g at a time before any successor of the group is
+  // formed, so one LDS round trip serves up to g successors
+  auto run_group = [&](auto g, const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t n) {
+    constexpr int kG = decltype(g)::value;
+    for (uint32_t t = 0; cur < hi && __ballot(t < n); t += kG) {
+      uint32_t d[kG];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) d[k] = t + k < n ? img[s0 + t + k] : 0u;
+      for (int k = 0; k < kG; ++k) d[k] = t + k < n ? img[s0 + t + k] : 0u;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kG; ++k) {
         uint32_t succ[S];
 #pragma unroll
         for (int x = 0; x < S; ++x) succ[x] = from[x];
@@ -156,6 +157,15 @@ __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t 
         put(t + k < n, succ);
       }
     }
+  };
+  // the group is as wide as the wavefront's widest run needs, up to four: a
+  // slot of a group that no lane fills still costs its wavefront-wide
+  // numbering, and narrow runs (one or two targets) are the common case
+  auto run = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t n) {
+    if (below(n)) return;
+    if (!__ballot(n > 1)) run_group(std::integral_constant<int, 1>{}, from, f, s0, n);
+    else if (!__ballot(n > 2)) run_group(std::integral_constant<int, 2>{}, from, f, s0, n);
+    else run_group(std::integral_constant<int, 4>{}, from, f, s0, n);
   };
   for (uint32_t p = 0; p < P && cur < hi; ++p) {
     const uint32_t f = img[4 + p];
