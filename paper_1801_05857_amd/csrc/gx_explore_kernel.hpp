@@ -111,7 +111,8 @@ __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) 
 // least the total.  Must be reached by the whole wavefront; a lane without a
 // state passes has = false.  Optional outputs: *total, the wavefront's
 // successors (without the window: all of them), and *mine, this lane's.
-template <int S, bool kWindow>
+// kMaxGroup (1 or 4): the widest group of targets read per LDS round trip.
+template <int S, bool kWindow, int kMaxGroup = 4>
 __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t (&sw)[S],
                                             bool has, uint32_t* out, uint32_t lo, uint32_t hi,
                                             uint32_t* total = nullptr, uint32_t* mine = nullptr) {
@@ -160,10 +161,12 @@ __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t 
   };
   // the group is as wide as the wavefront's widest run needs, up to four: a
   // slot of a group that no lane fills still costs its wavefront-wide
-  // numbering, and narrow runs (one or two targets) are the common case
+  // numbering, and narrow runs (one or two targets) are the common case.
+  // kMaxGroup = 1: always one (the latency-bound one-workgroup levels, where
+  // the three inlined group widths cost more than wider groups save)
   auto run = [&](const uint32_t (&from)[S], uint32_t f, uint32_t s0, uint32_t n) {
     if (below(n)) return;
-    if (!__ballot(n > 1)) run_group(std::integral_constant<int, 1>{}, from, f, s0, n);
+    if (kMaxGroup == 1 || !__ballot(n > 1)) run_group(std::integral_constant<int, 1>{}, from, f, s0, n);
     else if (!__ballot(n > 2)) run_group(std::integral_constant<int, 2>{}, from, f, s0, n);
     else run_group(std::integral_constant<int, 4>{}, from, f, s0, n);
   };

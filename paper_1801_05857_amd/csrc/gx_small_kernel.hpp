@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kSmallThreads) void lds_levels_kernel(SmallArgs a) 
         // every state's successors fit one chunk: emitted at once, counted
         // on the way (this lane's for the deadlock test)
         uint32_t c = 0;
-        emit_window<S, false>(img, sw, has, stage, 0, kChunk, &total, &c);
+        emit_window<S, false, 1>(img, sw, has, stage, 0, kChunk, &total, &c);
         if (has && c == 0) {
           const uint64_t d = atomicAdd(ctr_at(a.ctr, kCtrDead), 1ull);
           if (d < a.dead_cap) store_slot<S>(a.dead + d * S, sw);
