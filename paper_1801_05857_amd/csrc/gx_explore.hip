@@ -643,6 +643,12 @@ static gx_status explore_impl(const gx_network* net, gx_table* t, const gx_explo
   ap.n_keys = nullptr;  // per slice: the successor counter its generation uses
   ap.ctr = eb.ctr;
   ap.count_trans = g.dedup ? 0u : 1u;  // the filtered generation counts its own
+  // a three-word state's successors go through the successor buffer as three
+  // words, not as their four-word slots (a quarter less written and read;
+  // the filtered generation stages whole slots)
+  g.succ_words = S == 4 && t->w == 3 && !g.dedup ? 3u : S;
+  g.pad = 0;
+  ap.key_words = g.succ_words;
   const uint32_t dedup_words =
       g.dedup ? 4u * (S == 1 ? gx::dedup_entries<1>() : S == 2 ? gx::dedup_entries<2>()
                                                                : gx::dedup_entries<4>())

@@ -86,6 +86,19 @@ __device__ __forceinline__ void load_slot(const uint32_t* p, uint32_t (&k)[S]) {
   }
 }
 
+// A three-word state's words without its slot's fourth (zero) word, and back.
+template <int S>
+__device__ __forceinline__ void store_words3(uint32_t* p, const uint32_t (&k)[S]) {
+#pragma unroll
+  for (int x = 0; x < 3 && x < S; ++x) p[x] = k[x];
+}
+
+template <int S>
+__device__ __forceinline__ void load_words3(const uint32_t* p, uint32_t (&k)[S]) {
+#pragma unroll
+  for (int x = 0; x < S; ++x) k[x] = x < 3 ? p[x] : 0u;
+}
+
 template <int S>
 __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) {
   if constexpr (S == 4) {
@@ -112,10 +125,13 @@ __device__ __forceinline__ void store_slot(uint32_t* p, const uint32_t (&k)[S]) 
 // state passes has = false.  Optional outputs: *total, the wavefront's
 // successors (without the window: all of them), and *mine, this lane's.
 // kMaxGroup (1 or 4): the widest group of targets read per LDS round trip.
+// out_words: words per successor in out (S; or 3 with S = 4, the three words
+// of a three-word state without its slot's zero fourth word).
 template <int S, bool kWindow, int kMaxGroup = 4>
 __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t (&sw)[S],
                                             bool has, uint32_t* out, uint32_t lo, uint32_t hi,
-                                            uint32_t* total = nullptr, uint32_t* mine = nullptr) {
+                                            uint32_t* total = nullptr, uint32_t* mine = nullptr,
+                                            uint32_t out_words = S) {
   const uint32_t P = img[0], R = img[1];
   uint32_t cur = 0;  // successors the wavefront has numbered (the same in every lane)
   uint32_t own = 0;  // this lane's
@@ -124,7 +140,12 @@ __device__ __forceinline__ void emit_window(const uint32_t* img, const uint32_t 
     const uint32_t k = cur + __builtin_amdgcn_mbcnt_hi(
                                  static_cast<uint32_t>(m >> 32),
                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
-    if (act && k >= lo && k < hi) store_slot<S>(out + static_cast<uint64_t>(k - lo) * S, succ);
+    if (act && k >= lo && k < hi) {
+      if (S == 4 && out_words == 3)
+        store_words3<S>(out + static_cast<uint64_t>(k - lo) * 3, succ);
+      else
+        store_slot<S>(out + static_cast<uint64_t>(k - lo) * S, succ);
+    }
     cur += static_cast<uint32_t>(__popcll(m));
     if (mine) own += act ? 1u : 0u;
   };
@@ -464,6 +485,8 @@ struct GenArgs {
   // next-frontier tail at the first slice of a level.  No host-side clears.
   uint32_t succ_ctr;
   uint32_t reset_tail;
+  uint32_t succ_words;  // words per successor in succ (S, or 3: see emit_window)
+  uint32_t pad;
 };
 
 // Load, count and deadlock-check this lane's frontier state.
@@ -593,7 +616,8 @@ __global__ __launch_bounds__(256) void gen_level_kernel(GenArgs a) {
   uint64_t base = group_base;
   if (base == ~0ull || total == 0) return;
   for (int w = 0; w < wave; ++w) base += wave_total[w];
-  emit_window<S, false>(img, sw, first + lane < a.n_in, a.succ + base * S, 0, total);
+  emit_window<S, false>(img, sw, first + lane < a.n_in, a.succ + base * a.succ_words, 0, total,
+                        nullptr, nullptr, a.succ_words);
 }
 
 struct AppendArgs {
@@ -605,6 +629,7 @@ struct AppendArgs {
   uint64_t cap_out;        // states
   uint64_t* ctr;           // the level's counters (see ctr_at)
   uint32_t count_trans;    // add n_keys to the transition count (unfiltered slices)
+  uint32_t key_words;      // words per key in keys (S, or 3: see emit_window)
 };
 
 constexpr uint32_t kAppendKeys = 256;  // NEW keys a wavefront gathers in LDS
@@ -648,7 +673,12 @@ __global__ __launch_bounds__(256) void append_kernel(AppendArgs a) {
     uint32_t key[S];
 #pragma unroll
     for (int x = 0; x < S; ++x) key[x] = 0;
-    if (act) load_slot<S>(a.keys + idx * S, key);
+    if (act) {
+      if (S == 4 && a.key_words == 3)
+        load_words3<S>(a.keys + idx * 3, key);
+      else
+        load_slot<S>(a.keys + idx * S, key);
+    }
     const uint8_t r = find_or_put_lanes<S, B, G, U>(a.t, key, act, st);
     const bool is_new = act && r == kNew;
     full |= act && r == kFull;
