@@ -374,12 +374,14 @@ def explore_bytes_per_state(f: float, B: int, S: int) -> float:
     return f * max(4 * B, GRANULE) + 2 * 4 * S + GRANULE
 
 
-def successor_buffer_bytes_per_state(f: float, S: int) -> float:
+def successor_buffer_bytes_per_state(f: float, w: int) -> float:
     """HBM bytes per explored state that the two-kernel level adds on top of
     the algorithmic ones: every successor is written to the successor buffer
-    and read back by the probe kernel (4S bytes each way).  Overhead of this
-    implementation, not counted in the roofline."""
-    return f * 2 * 4 * S
+    and read back by the probe kernel (its w words each way; without the
+    local duplicate filter the buffer holds w words per successor, not the
+    slot's S).  Overhead of this implementation, not counted in the
+    roofline."""
+    return f * 2 * 4 * w
 
 
 def roofline_of(states: int, bytes_per_state_total: float, seconds: float) -> dict:
@@ -431,7 +433,7 @@ def run_explore_leg(gx, torch, W, live=8, slots=None):
            "probes_per_lookup": round(st.probes / max(1, st.lookups), 4),
            "load_factor": round(r.n_states / info.n_slots, 3),
            "roofline": roofline_of(r.n_states, r.n_states * bps, dt),
-           "successor_buffer_bytes_per_state": round(successor_buffer_bytes_per_state(f, S), 1)}
+           "successor_buffer_bytes_per_state": round(successor_buffer_bytes_per_state(f, w), 1)}
     traffic = measured_explore_traffic() if live == 8 and slots == W.LARGE_TABLE_SLOTS else None
     out["roofline"]["traffic"] = traffic
     out["roofline"]["traffic_unit"] = ("HBM bytes per exploration (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
