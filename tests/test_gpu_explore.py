@@ -138,6 +138,24 @@ def test_random_networks_every_specialisation(dev, w, B, G):
     assert got.words_per_state == w
 
 
+@pytest.mark.parametrize("slice_states", [0, 1000])
+@pytest.mark.parametrize("B,G", [(16, 4), (32, 8)])
+def test_four_word_states_through_both_kernels(dev, B, G, slice_states):
+    """Four-word states with levels of up to 21,087 states, past the
+    one-workgroup limit, so they take the generation and probe kernels: the
+    successor buffer holds whole four-word slots there (three-word states
+    hold three words; the w = 3 networks above cover those)."""
+    net = W.random_lts(405, 16, 64, [3] * 4 + [2] * 12, 3, 32, 0.25, 0.0)
+    want = oracle.explore(net, want_visited=True)
+    assert want.words == 4 and max(want.levels) > 4096
+    with gx.Table(4, B, 2 * want.n_states, subgroup=G, max_hashes=64) as t:
+        got = gx.explore(net, t, slice_states=slice_states)
+        assert got.n_states == want.n_states
+        assert got.levels.tolist() == want.levels.tolist()
+        assert got.n_transitions == want.n_transitions
+        assert np.array_equal(t.dump(), want.visited)
+
+
 @pytest.mark.parametrize("seed", [2, 8, 11, 13, 14, 20, 24, 25])
 def test_random_networks_with_deadlocks(dev, seed):
     net = W.random_lts(seed, 3 + seed % 3, 8, 6, 2, 8, 0.5, 0.4)
