@@ -138,6 +138,21 @@ def test_random_networks_every_specialisation(dev, w, B, G):
     assert got.words_per_state == w
 
 
+@pytest.mark.parametrize("live,slice_states", [(2, 1), (3, 64)])
+def test_tiny_slices(dev, live, slice_states):
+    """Slices of one state (4,096-state network, levels up to 924 states,
+    past the one-workgroup limit of a few hundred) and of 64 states (157,464
+    states): a launch pair per slice."""
+    net = W.random_lts(303, 12, 64, live, 3, 32, 0.25, 0.1)
+    want = oracle.explore(net, want_visited=True)
+    with gx.Table(want.words, 16, 2 * want.n_states, subgroup=4, max_hashes=64) as t:
+        got = gx.explore(net, t, slice_states=slice_states)
+        assert got.levels.tolist() == want.levels.tolist()
+        assert got.n_transitions == want.n_transitions
+        assert np.array_equal(got.deadlocks, want.deadlocks)
+        assert np.array_equal(t.dump(), want.visited)
+
+
 @pytest.mark.parametrize("slice_states", [0, 1000])
 @pytest.mark.parametrize("B,G", [(16, 4), (32, 8)])
 def test_four_word_states_through_both_kernels(dev, B, G, slice_states):
