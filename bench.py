@@ -277,7 +277,7 @@ def random_read_ceiling(gx, torch, granule: int, gib: int = 2):
     return rate
 
 
-def run_tiny(gx, torch, W, reps=10):
+def run_tiny(gx, torch, W, reps=100):
     """The tiny configuration (four 8-state cycles with two rendezvous, one
     word, table of 2^16 words, buckets of 32): microseconds per exploration,
     median of `reps` after warm-up."""
